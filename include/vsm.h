@@ -1,0 +1,175 @@
+/*
+ * vsm.h -- C ABI of the MI355X (gfx950) library for smoothing Z(3)
+ * centre-vortex gauge fields, after "Smoothing algorithms for projected
+ * center-vortex gauge fields" (A. Virgili, W. Kamleh, D. Leinweber,
+ * arXiv:2203.09764).
+ *
+ * The calls follow the paper's statement of the problem: take a Z(3) field
+ * (Sec. I), precondition it (Sec. IV), smooth it with stout / over-improved stout
+ * or MaxReTr (cooling) updates, annealed or smeared, with or without vortex
+ * preservation (Sec. II, III, V, VI), and measure it (Sec. I, V.A).
+ *
+ * Conventions for every call
+ *   dims[4]   lattice extents (Lx, Ly, Lz, Lt), host array.  Every extent must be
+ *             >= 4 and Lx a multiple of 4; the annealed schedule needs every
+ *             extent to be a multiple of 4.  9 * V * sizeof(entry) must stay
+ *             below 2^31 bytes (V < 14.9M sites in FP64, < 29.8M in FP32).
+ *   site      s = x + Lx*(y + Ly*(z + Lz*t)); direction mu = 0..3 = (x, y, z, t).
+ *   precision VSM_FP64 (all arithmetic and storage FP64) or VSM_FP32_BULK
+ *             (links stored and staples / products computed in FP32; the
+ *             Cayley-Hamilton coefficients, reunitarisation, MaxReTr and all
+ *             measurement sums in FP64).
+ *   pointers  "device" means memory of the current HIP device (for example a
+ *             torch CUDA tensor's data_ptr()); the library never allocates,
+ *             frees or keeps caller buffers.
+ *   links     device buffer of vsm_links_bytes(dims, precision) bytes in the
+ *             library's internal layout; only the calls below read or write it.
+ *   stream    hipStream_t passed as void* (NULL = default stream).  Every call
+ *             is asynchronous on that stream; none synchronises the host.
+ *   status    0 (VSM_OK) on success, a negative VSM_E_* code otherwise.  On an
+ *             error nothing has been enqueued.  Numerical anomalies (NaN links,
+ *             traces on a sector boundary) are not errors: they are counted in
+ *             vsm_stats.
+ */
+#ifndef VSM_H
+#define VSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VSM_OK 0
+#define VSM_E_DIMS (-1)      /* extents not allowed for the layout or schedule       */
+#define VSM_E_PARAM (-2)     /* a parameter outside its domain                       */
+#define VSM_E_NULL (-3)      /* a required pointer is NULL                           */
+#define VSM_E_WORKSPACE (-4) /* workspace smaller than vsm_workspace_bytes          */
+#define VSM_E_BUDGET (-5)    /* serving: job larger than the whole memory budget     */
+#define VSM_E_HIP (-6)       /* a HIP call failed; see vsm_last_hip_error()          */
+#define VSM_E_STATE (-7)     /* serving: unknown job or server shut down             */
+
+#define VSM_FP64 0
+#define VSM_FP32_BULK 1
+
+#define VSM_JACOBI 0   /* smearing: every link from the previous sweep (Sec. III.A)   */
+#define VSM_ANNEALED 1 /* annealing: masked subsets updated in place (Sec. III.A)    */
+
+#define VSM_STOUT 0    /* U' = exp(rho Q) U (Eq. stout, Eq. generator)                */
+#define VSM_MAXRETR 1  /* MaxReTr of V = (1-alpha) U + alpha/6 Sigma (Sec. III);
+                          alpha = 1 is cooling                                        */
+
+/* How a sweep updates links. */
+typedef struct {
+  int32_t order;     /* VSM_JACOBI or VSM_ANNEALED                                    */
+  int32_t update;    /* VSM_STOUT or VSM_MAXRETR                                      */
+  int32_t vp;        /* 1: vortex-preserving accept/reject of Sec. VI                 */
+  int32_t su2_loops; /* MaxReTr: loops over the three SU(2) subgroups (paper: 3)      */
+  double u0;         /* mean link in the rectangle weight of Eq. (over-improvement)  */
+  double alpha;      /* MaxReTr: APE blocking fraction of Eq. (V)                     */
+} vsm_schedule;
+
+/* One measurement record (64 bytes, host or device). */
+typedef struct {
+  double plaq;              /* <P> = (1/18V) sum_x sum_{mu<nu} Re Tr P_{mu nu}(x)         */
+  double action;            /* <S>/beta = (1/36V) sum_x sum_{mu<nu} Re Tr[1 - P_{mu nu}]  */
+  double max_unitarity;     /* max over links and entries of |U^dag U - 1|               */
+  double sweep;             /* sweeps done when the record was taken                    */
+  int64_t flux_mismatch;    /* plaquettes whose vortex flux differs from the original   */
+  int64_t undefined_sector; /* links whose trace lies on a sector boundary or is 0      */
+  int64_t rejected;         /* vortex-preservation rejections since the last record     */
+  int64_t nonfinite;        /* links with a non-finite entry                            */
+} vsm_stats;
+
+/* Library version string; never NULL. */
+const char *vsm_version(void);
+/* Text of a status code; never NULL. */
+const char *vsm_strerror(int status);
+/* hipError_t of the last VSM_E_HIP returned on this thread (0 if none). */
+int vsm_last_hip_error(void);
+
+/* 0 if dims are allowed for `order` (VSM_JACOBI or VSM_ANNEALED) and precision,
+ * otherwise VSM_E_DIMS or VSM_E_NULL.  Host only. */
+int vsm_check_dims(const int32_t dims[4], int32_t order, int32_t precision);
+/* Bytes of the internal link buffer (0 for invalid arguments). */
+size_t vsm_links_bytes(const int32_t dims[4], int32_t precision);
+/* Bytes of device workspace that vsm_smooth / vsm_measure / vsm_pass need for
+ * this order: reduction slots and counters, plus a second link buffer for
+ * VSM_JACOBI.  0 for invalid arguments. */
+size_t vsm_workspace_bytes(const int32_t dims[4], int32_t precision, int32_t order);
+
+/* Copy links in from / out to the canonical interchange layout:
+ * canon = device complex128 [4][V][3][3] (row-major 3x3, re/im interleaved).
+ * FP32_BULK rounds on the way in and widens exactly on the way out. */
+int vsm_set_links(const int32_t dims[4], int32_t precision, const double *canon_dev, void *links_dev,
+                  void *stream);
+int vsm_get_links(const int32_t dims[4], int32_t precision, const void *links_dev, double *canon_dev,
+                  void *stream);
+
+/* Sec. I, Eq. (centre_project): U_mu(x) = e^{2 pi i n_mu(x)/3} 1 from the charges
+ * z3_dev = device int8 [4][V] with values in {-1, 0, 1}.  Values outside that set
+ * are not checked on the device (they are treated as the nearest valid one). */
+int vsm_load_z3(const int32_t dims[4], int32_t precision, const int8_t *z3_dev, void *links_dev,
+                void *stream);
+
+/* Sec. IV: centrifuge preconditioning of the Z(3) field with charges z3_dev.
+ * For every link, with lambda = 2 pi n/3 and the staple phase sigma = 2 pi m/18
+ * (m the integer sum over the six staples of the neighbouring charges),
+ * lambda^j = (1-omega) lambda + omega sigma, lambda^k = (1+omega) lambda - omega sigma
+ * (Eqs. lambda_j, lambda_k), the third phase unchanged.  pair_dev = device int8
+ * [4][V] with the random pair per link, 0, 1, 2 = (j,k) = (1,2), (2,3), (3,1).
+ * |omega| must be below 1/4 (Sec. IV.A): then omega |m - 6n| < 6 holds for every
+ * link and the centre sector of every link is kept.  m_dev (device int32 [4][V])
+ * receives m when not NULL.  Overwrites links_dev. */
+int vsm_precondition(const int32_t dims[4], int32_t precision, const int8_t *z3_dev,
+                     const int8_t *pair_dev, double omega, void *links_dev, int32_t *m_dev,
+                     void *stream);
+
+/* Sec. V.C: U_mu(x) -> G(x) U_mu(x) G^dagger(x + mu) in place, gauge_dev = device
+ * complex128 [V][3][3], canonical site order.  Test and recipe utility. */
+int vsm_gauge_transform(const int32_t dims[4], int32_t precision, void *links_dev,
+                        const double *gauge_dev, void *stream);
+
+/* n_sweeps sweeps of the update chosen by *sched (host pointer) on links_dev.
+ *   rho  stout step (flow-time step of the Euler integration, Sec. V.B).
+ *   eps  over-improvement parameter of Eq. (over-improvement): staple weights
+ *        (5 - 2 eps)/3 and (eps - 1)/(12 u0^2); eps = 1 gives the plain staples
+ *        of Eq. (plaq_staples).
+ *   VSM_ANNEALED: per sweep, for mu = 0..3, the subsets c = 0, 2, 1, 3 with
+ *        c = (2 x_mu + sum_{nu != mu} x_nu) mod 4 (no two links of a subset share a
+ *        staple path), each updated in place.  VSM_JACOBI: every link from the
+ *        previous sweep's field.
+ *   vp   with sched->vp, a candidate is kept only if its Z(3) projection equals
+ *        the original charge z3_dev (Sec. VI); with gauge_dev != NULL the test
+ *        projects G^dagger(x) U' G(x + mu) (the field is in that random gauge).
+ *   measure_every > 0: after every measure_every-th sweep a vsm_stats record is
+ *        written to stats_dev (device, n_sweeps / measure_every records).
+ *   workspace_dev: device, at least vsm_workspace_bytes(dims, precision, order).
+ * z3_dev is required when vp or measurement is on. */
+int vsm_smooth(const int32_t dims[4], int32_t precision, void *links_dev, const int8_t *z3_dev,
+               const double *gauge_dev, void *workspace_dev, size_t workspace_bytes,
+               int32_t n_sweeps, double rho, double eps, const vsm_schedule *sched,
+               int32_t measure_every, vsm_stats *stats_dev, void *stream);
+
+/* One annealing subset (direction mu, subset colour) of the update chosen by
+ * *sched, in place; the building block of an annealed sweep.  The rejection
+ * count accumulates in the workspace until the next measurement. */
+int vsm_pass(const int32_t dims[4], int32_t precision, void *links_dev, const int8_t *z3_dev,
+             const double *gauge_dev, void *workspace_dev, size_t workspace_bytes, int32_t mu,
+             int32_t colour, double rho, double eps, const vsm_schedule *sched, void *stream);
+
+/* Sec. I, V.A: one vsm_stats record of links_dev into stats_dev (device); the
+ * vortex flux p_{mu nu}(x) in {-1, 0, 1} of the current links' centre projections
+ * into flux_dev (device int8 [6][V], planes 01, 02, 03, 12, 13, 23; -128 where a
+ * sector is undefined) when not NULL.  The rejected field reports the count
+ * accumulated in the workspace since the last record and clears it. */
+int vsm_measure(const int32_t dims[4], int32_t precision, const void *links_dev, const int8_t *z3_dev,
+                void *workspace_dev, size_t workspace_bytes, vsm_stats *stats_dev,
+                int8_t *flux_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VSM_H */

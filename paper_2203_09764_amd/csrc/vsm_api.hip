@@ -1,0 +1,270 @@
+// vsm_api.hip -- the C ABI of include/vsm.h: validation, workspace layout and the
+// launch sequences of the smoothing path.  No entry point allocates memory.
+#include <math.h>
+#include <string.h>
+
+#include "vsm.h"
+#include "vsm_launch.h"
+
+using namespace vsm;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_status() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return VSM_E_HIP;
+  }
+  return VSM_OK;
+}
+
+size_t entry_bytes(int32_t precision) { return precision == VSM_FP64 ? 16 : 8; }
+
+bool valid_precision(int32_t p) { return p == VSM_FP64 || p == VSM_FP32_BULK; }
+
+int check_dims_impl(const int32_t dims[4], int32_t order, int32_t precision) {
+  if (!dims) return VSM_E_NULL;
+  if (!valid_precision(precision)) return VSM_E_PARAM;
+  if (order != VSM_JACOBI && order != VSM_ANNEALED) return VSM_E_PARAM;
+  uint64_t V = 1;
+  for (int d = 0; d < 4; ++d) {
+    if (dims[d] < 4) return VSM_E_DIMS;
+    if (order == VSM_ANNEALED && dims[d] % 4) return VSM_E_DIMS;
+    V *= (uint64_t)dims[d];
+  }
+  if (dims[0] % 4) return VSM_E_DIMS;
+  if (9ull * V * entry_bytes(precision) >= (1ull << 31)) return VSM_E_DIMS;
+  return VSM_OK;
+}
+
+Geo make_geo(const int32_t dims[4]) {
+  Geo g;
+  for (int d = 0; d < 4; ++d) g.L[d] = dims[d];
+  g.Xq = dims[0] / 4;
+  g.V = (uint32_t)dims[0] * (uint32_t)dims[1] * (uint32_t)dims[2] * (uint32_t)dims[3];
+  g.V4 = g.V / 4;
+  g.st[0] = 1;
+  g.st[1] = (uint32_t)g.Xq;
+  g.st[2] = (uint32_t)g.Xq * (uint32_t)dims[1];
+  g.st[3] = (uint32_t)g.Xq * (uint32_t)dims[1] * (uint32_t)dims[2];
+  return g;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Workspace: [0, 256) counters (rejections at 0); then the measurement block
+// partials; then, for the smearing schedule, a second link buffer.
+struct WsLayout {
+  size_t counters, partials, field, total;
+};
+
+WsLayout ws_layout(const int32_t dims[4], int32_t precision, int32_t order) {
+  const Geo g = make_geo(dims);
+  WsLayout w;
+  w.counters = 0;
+  w.partials = 256;
+  w.field = align256(w.partials + (size_t)measure_blocks(g) * partial_bytes());
+  w.total = w.field;
+  if (order == VSM_JACOBI) w.total += align256(36ull * g.V * entry_bytes(precision));
+  return w;
+}
+
+bool is_fin(double v) { return isfinite(v) != 0; }
+
+int check_sched(const vsm_schedule* s) {
+  if (!s) return VSM_E_NULL;
+  if (s->order != VSM_JACOBI && s->order != VSM_ANNEALED) return VSM_E_PARAM;
+  if (s->update != VSM_STOUT && s->update != VSM_MAXRETR) return VSM_E_PARAM;
+  if (!is_fin(s->u0) || s->u0 == 0.0) return VSM_E_PARAM;
+  if (s->update == VSM_MAXRETR && (!is_fin(s->alpha) || s->su2_loops < 0)) return VSM_E_PARAM;
+  return VSM_OK;
+}
+
+UpdParams make_params(double rho, double eps, const vsm_schedule* s) {
+  UpdParams p;
+  p.cp = (5.0 - 2.0 * eps) / 3.0;
+  p.cr = (eps - 1.0) / (12.0 * s->u0 * s->u0);
+  p.rho = rho;
+  p.alpha = s->alpha;
+  p.update = s->update == VSM_MAXRETR ? 1 : 0;
+  p.oi = p.cr != 0.0 ? 1 : 0;
+  p.vp = s->vp ? 1 : 0;
+  p.loops = s->su2_loops;
+  return p;
+}
+
+const int kColours[4] = {0, 2, 1, 3};
+
+}  // namespace
+
+extern "C" {
+
+const char* vsm_version(void) { return "vsm 1.0 (gfx950)"; }
+
+const char* vsm_strerror(int status) {
+  switch (status) {
+    case VSM_OK: return "ok";
+    case VSM_E_DIMS: return "lattice extents not allowed (>= 4, Lx % 4 == 0, all % 4 == 0 when annealed, 9*V*entry < 2^31)";
+    case VSM_E_PARAM: return "parameter outside its domain";
+    case VSM_E_NULL: return "required pointer is NULL";
+    case VSM_E_WORKSPACE: return "workspace too small";
+    case VSM_E_BUDGET: return "job exceeds the memory budget";
+    case VSM_E_HIP: return "HIP call failed (see vsm_last_hip_error)";
+    case VSM_E_STATE: return "unknown job or server state";
+    default: return "unknown status";
+  }
+}
+
+int vsm_last_hip_error(void) { return g_last_hip; }
+
+int vsm_check_dims(const int32_t dims[4], int32_t order, int32_t precision) {
+  return check_dims_impl(dims, order, precision);
+}
+
+size_t vsm_links_bytes(const int32_t dims[4], int32_t precision) {
+  if (check_dims_impl(dims, VSM_JACOBI, precision) != VSM_OK) return 0;
+  const Geo g = make_geo(dims);
+  return 36ull * g.V * entry_bytes(precision);
+}
+
+size_t vsm_workspace_bytes(const int32_t dims[4], int32_t precision, int32_t order) {
+  if (check_dims_impl(dims, order, precision) != VSM_OK) return 0;
+  return ws_layout(dims, precision, order).total;
+}
+
+int vsm_set_links(const int32_t dims[4], int32_t precision, const double* canon_dev, void* links_dev,
+                  void* stream) {
+  int rc = check_dims_impl(dims, VSM_JACOBI, precision);
+  if (rc) return rc;
+  if (!canon_dev || !links_dev) return VSM_E_NULL;
+  launch_set_links(precision, make_geo(dims), canon_dev, links_dev, (hipStream_t)stream);
+  return hip_status();
+}
+
+int vsm_get_links(const int32_t dims[4], int32_t precision, const void* links_dev, double* canon_dev,
+                  void* stream) {
+  int rc = check_dims_impl(dims, VSM_JACOBI, precision);
+  if (rc) return rc;
+  if (!canon_dev || !links_dev) return VSM_E_NULL;
+  launch_get_links(precision, make_geo(dims), links_dev, canon_dev, (hipStream_t)stream);
+  return hip_status();
+}
+
+int vsm_load_z3(const int32_t dims[4], int32_t precision, const int8_t* z3_dev, void* links_dev,
+                void* stream) {
+  int rc = check_dims_impl(dims, VSM_JACOBI, precision);
+  if (rc) return rc;
+  if (!z3_dev || !links_dev) return VSM_E_NULL;
+  launch_load_z3(precision, make_geo(dims), z3_dev, links_dev, (hipStream_t)stream);
+  return hip_status();
+}
+
+int vsm_precondition(const int32_t dims[4], int32_t precision, const int8_t* z3_dev,
+                     const int8_t* pair_dev, double omega, void* links_dev, int32_t* m_dev,
+                     void* stream) {
+  int rc = check_dims_impl(dims, VSM_JACOBI, precision);
+  if (rc) return rc;
+  if (!z3_dev || !pair_dev || !links_dev) return VSM_E_NULL;
+  if (!is_fin(omega) || !(fabs(omega) < 0.25)) return VSM_E_PARAM;
+  launch_centrifuge(precision, make_geo(dims), z3_dev, pair_dev, omega, links_dev, m_dev,
+                    (hipStream_t)stream);
+  return hip_status();
+}
+
+int vsm_gauge_transform(const int32_t dims[4], int32_t precision, void* links_dev,
+                        const double* gauge_dev, void* stream) {
+  int rc = check_dims_impl(dims, VSM_JACOBI, precision);
+  if (rc) return rc;
+  if (!links_dev || !gauge_dev) return VSM_E_NULL;
+  launch_gauge(precision, make_geo(dims), links_dev, gauge_dev, (hipStream_t)stream);
+  return hip_status();
+}
+
+int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const int8_t* z3_dev,
+               const double* gauge_dev, void* workspace_dev, size_t workspace_bytes,
+               int32_t n_sweeps, double rho, double eps, const vsm_schedule* sched,
+               int32_t measure_every, vsm_stats* stats_dev, void* stream) {
+  int rc = check_sched(sched);
+  if (rc) return rc;
+  rc = check_dims_impl(dims, sched->order, precision);
+  if (rc) return rc;
+  if (!links_dev || !workspace_dev) return VSM_E_NULL;
+  if (n_sweeps < 0 || measure_every < 0 || !is_fin(rho) || !is_fin(eps)) return VSM_E_PARAM;
+  if ((sched->vp || measure_every > 0) && !z3_dev) return VSM_E_NULL;
+  if (measure_every > 0 && !stats_dev) return VSM_E_NULL;
+  const WsLayout w = ws_layout(dims, precision, sched->order);
+  if (workspace_bytes < w.total) return VSM_E_WORKSPACE;
+  const Geo g = make_geo(dims);
+  const UpdParams p = make_params(rho, eps, sched);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace_dev;
+  unsigned long long* rej = (unsigned long long*)(ws + w.counters);
+  VsmStatsDev* out = (VsmStatsDev*)stats_dev;
+  launch_zero_u64(rej, 1, st);
+  void* cur = links_dev;
+  void* other = ws + w.field;
+  int rec = 0;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    if (sched->order == VSM_JACOBI) {
+      for (int mu = 0; mu < 4; ++mu)
+        launch_update(precision, g, cur, other, z3_dev, gauge_dev, p, mu, 0, 1, rej, st);
+      void* t = cur;
+      cur = other;
+      other = t;
+    } else {
+      for (int mu = 0; mu < 4; ++mu)
+        for (int c = 0; c < 4; ++c)
+          launch_update(precision, g, links_dev, links_dev, z3_dev, gauge_dev, p, mu, kColours[c], 0,
+                        rej, st);
+    }
+    if (measure_every > 0 && (sw + 1) % measure_every == 0) {
+      launch_measure(precision, g, cur, z3_dev, ws + w.partials, nullptr, rej, out + rec, sw + 1, st);
+      ++rec;
+    }
+  }
+  if (cur != links_dev) {
+    if (hipMemcpyAsync(links_dev, cur, 36ull * g.V * entry_bytes(precision), hipMemcpyDeviceToDevice,
+                       st) != hipSuccess)
+      return hip_status() ? VSM_E_HIP : VSM_E_HIP;
+  }
+  return hip_status();
+}
+
+int vsm_pass(const int32_t dims[4], int32_t precision, void* links_dev, const int8_t* z3_dev,
+             const double* gauge_dev, void* workspace_dev, size_t workspace_bytes, int32_t mu,
+             int32_t colour, double rho, double eps, const vsm_schedule* sched, void* stream) {
+  int rc = check_sched(sched);
+  if (rc) return rc;
+  rc = check_dims_impl(dims, VSM_ANNEALED, precision);
+  if (rc) return rc;
+  if (!links_dev || !workspace_dev) return VSM_E_NULL;
+  if (sched->vp && !z3_dev) return VSM_E_NULL;
+  if (mu < 0 || mu > 3 || colour < 0 || colour > 3 || !is_fin(rho) || !is_fin(eps)) return VSM_E_PARAM;
+  const WsLayout w = ws_layout(dims, precision, VSM_ANNEALED);
+  if (workspace_bytes < w.total) return VSM_E_WORKSPACE;
+  const UpdParams p = make_params(rho, eps, sched);
+  unsigned long long* rej = (unsigned long long*)((char*)workspace_dev + w.counters);
+  launch_update(precision, make_geo(dims), links_dev, links_dev, z3_dev, gauge_dev, p, mu, colour, 0, rej,
+                (hipStream_t)stream);
+  return hip_status();
+}
+
+int vsm_measure(const int32_t dims[4], int32_t precision, const void* links_dev, const int8_t* z3_dev,
+                void* workspace_dev, size_t workspace_bytes, vsm_stats* stats_dev, int8_t* flux_dev,
+                void* stream) {
+  int rc = check_dims_impl(dims, VSM_JACOBI, precision);
+  if (rc) return rc;
+  if (!links_dev || !z3_dev || !workspace_dev || !stats_dev) return VSM_E_NULL;
+  const WsLayout w = ws_layout(dims, precision, VSM_ANNEALED);
+  if (workspace_bytes < w.total) return VSM_E_WORKSPACE;
+  char* ws = (char*)workspace_dev;
+  launch_measure(precision, make_geo(dims), links_dev, z3_dev, ws + w.partials, flux_dev,
+                 (unsigned long long*)(ws + w.counters), (VsmStatsDev*)stats_dev, -1,
+                 (hipStream_t)stream);
+  return hip_status();
+}
+
+}  // extern "C"

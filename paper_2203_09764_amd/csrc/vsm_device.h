@@ -1,0 +1,441 @@
+// vsm_device.h -- device-side building blocks of the smoothing kernels (gfx950).
+//
+//  * 3x3 complex matrices in registers, templated on the storage/arithmetic type
+//    R (double for the FP64 form, float for the FP32-bulk form);
+//  * the internal link layout and its buffer-resource loads;
+//  * the Cayley-Hamilton exponential (Morningstar & Peardon, Phys. Rev. D 69,
+//    054501 (2004), the stout reference of Sec. II.A) with FP64 coefficients;
+//  * reunitarisation and the Z(3) sector test of Eq. (centre_element).
+//
+// Internal layout.  Sites are blocked by x mod 4 so that the links of one
+// annealing subset sit in contiguous runs:
+//   idx(x, y, z, t) = (x & 3) * V/4 + (x >> 2) + Xq * (y + Ly * (z + Lz * t)),  Xq = Lx/4.
+// Each direction mu owns 9 arrays of V complex entries (row-major 3x3 entry e):
+//   entry e of link (mu, idx) lives at element (mu * 9 + e) * V + idx,
+// stored as R2 = {re, im}.  A wave reads 64 consecutive idx values of one entry
+// in one 1 KiB (FP64) or 512 B (FP32) coalesced request.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vsm {
+
+constexpr int kUndef = -128;
+constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9-family raw buffer descriptor
+
+// ------------------------------------------------------------------ complex
+
+template <typename R>
+struct Cx {
+  R re, im;
+};
+
+template <typename R>
+struct M3 {
+  Cx<R> a[9];
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cx(R re, R im) {
+  return Cx<R>{re, im};
+}
+
+// acc += x * y
+template <typename R>
+__device__ __forceinline__ void cfma(Cx<R>& acc, const Cx<R>& x, const Cx<R>& y) {
+  acc.re = fma(x.re, y.re, acc.re);
+  acc.re = fma(-x.im, y.im, acc.re);
+  acc.im = fma(x.re, y.im, acc.im);
+  acc.im = fma(x.im, y.re, acc.im);
+}
+// acc += x * conj(y)
+template <typename R>
+__device__ __forceinline__ void cfma_c2(Cx<R>& acc, const Cx<R>& x, const Cx<R>& y) {
+  acc.re = fma(x.re, y.re, acc.re);
+  acc.re = fma(x.im, y.im, acc.re);
+  acc.im = fma(x.im, y.re, acc.im);
+  acc.im = fma(-x.re, y.im, acc.im);
+}
+// acc += conj(x) * y
+template <typename R>
+__device__ __forceinline__ void cfma_c1(Cx<R>& acc, const Cx<R>& x, const Cx<R>& y) {
+  acc.re = fma(x.re, y.re, acc.re);
+  acc.re = fma(x.im, y.im, acc.re);
+  acc.im = fma(x.re, y.im, acc.im);
+  acc.im = fma(-x.im, y.re, acc.im);
+}
+
+// ------------------------------------------------------------------ 3x3 algebra
+
+template <typename R>
+__device__ __forceinline__ M3<R> mzero() {
+  M3<R> r;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) r.a[e] = cx<R>(R(0), R(0));
+  return r;
+}
+
+// x * y
+template <typename R>
+__device__ __forceinline__ M3<R> mul_nn(const M3<R>& x, const M3<R>& y) {
+  M3<R> r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Cx<R> acc = cx<R>(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma(acc, x.a[3 * i + k], y.a[3 * k + j]);
+      r.a[3 * i + j] = acc;
+    }
+  return r;
+}
+
+// x * y^dagger
+template <typename R>
+__device__ __forceinline__ M3<R> mul_nd(const M3<R>& x, const M3<R>& y) {
+  M3<R> r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Cx<R> acc = cx<R>(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma_c2(acc, x.a[3 * i + k], y.a[3 * j + k]);
+      r.a[3 * i + j] = acc;
+    }
+  return r;
+}
+
+// x^dagger * y
+template <typename R>
+__device__ __forceinline__ M3<R> mul_dn(const M3<R>& x, const M3<R>& y) {
+  M3<R> r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Cx<R> acc = cx<R>(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma_c1(acc, x.a[3 * k + i], y.a[3 * k + j]);
+      r.a[3 * i + j] = acc;
+    }
+  return r;
+}
+
+// acc += c * x (real c)
+template <typename R>
+__device__ __forceinline__ void maxpy(M3<R>& acc, R c, const M3<R>& x) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    acc.a[e].re = fma(c, x.a[e].re, acc.a[e].re);
+    acc.a[e].im = fma(c, x.a[e].im, acc.a[e].im);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ Cx<R> mtrace(const M3<R>& x) {
+  return cx<R>(x.a[0].re + x.a[4].re + x.a[8].re, x.a[0].im + x.a[4].im + x.a[8].im);
+}
+
+template <typename D, typename S>
+__device__ __forceinline__ M3<D> mconvert(const M3<S>& x) {
+  M3<D> r;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) r.a[e] = cx<D>(D(x.a[e].re), D(x.a[e].im));
+  return r;
+}
+
+// ------------------------------------------------------------------ geometry
+
+struct Geo {
+  int L[4];       // extents (x, y, z, t)
+  int Xq;         // Lx / 4
+  uint32_t V;     // sites
+  uint32_t V4;    // V / 4
+  uint32_t st[4]; // idx stride of one step along y, z, t (st[0] unused)
+};
+
+// Contribution of coordinate value c along direction d to the blocked index.
+__device__ __forceinline__ int coord_term(const Geo& g, int d, int c) {
+  return d == 0 ? (int)((uint32_t)(c & 3) * g.V4) + (c >> 2) : c * (int)g.st[d];
+}
+
+// Index change for a step of k (|k| <= 2) along direction d from coordinate c.
+__device__ __forceinline__ int delta(const Geo& g, int d, int c, int k) {
+  int cn = c + k;
+  if (cn < 0) cn += g.L[d];
+  if (cn >= g.L[d]) cn -= g.L[d];
+  return coord_term(g, d, cn) - coord_term(g, d, c);
+}
+
+__device__ __forceinline__ uint32_t blocked_index(const Geo& g, const int c[4]) {
+  return (uint32_t)coord_term(g, 0, c[0]) + (uint32_t)c[1] * g.st[1] + (uint32_t)c[2] * g.st[2] +
+         (uint32_t)c[3] * g.st[3];
+}
+
+__device__ __forceinline__ void coords_of_blocked(const Geo& g, uint32_t idx, int c[4]) {
+  uint32_t q = idx / g.V4;
+  uint32_t j = idx - q * g.V4;
+  uint32_t xi = j % (uint32_t)g.Xq;
+  uint32_t r = j / (uint32_t)g.Xq;
+  c[0] = (int)(4 * xi + q);
+  c[1] = (int)(r % (uint32_t)g.L[1]);
+  r /= (uint32_t)g.L[1];
+  c[2] = (int)(r % (uint32_t)g.L[2]);
+  c[3] = (int)(r / (uint32_t)g.L[2]);
+}
+
+__device__ __forceinline__ uint32_t canonical_index(const Geo& g, const int c[4]) {
+  return (uint32_t)c[0] + (uint32_t)g.L[0] * ((uint32_t)c[1] + (uint32_t)g.L[1] * ((uint32_t)c[2] + (uint32_t)g.L[2] * (uint32_t)c[3]));
+}
+
+__device__ __forceinline__ void coords_of_canonical(const Geo& g, uint32_t s, int c[4]) {
+  c[0] = (int)(s % (uint32_t)g.L[0]);
+  s /= (uint32_t)g.L[0];
+  c[1] = (int)(s % (uint32_t)g.L[1]);
+  s /= (uint32_t)g.L[1];
+  c[2] = (int)(s % (uint32_t)g.L[2]);
+  c[3] = (int)(s / (uint32_t)g.L[2]);
+}
+
+// ------------------------------------------------------------------ link access
+
+template <typename R>
+struct R2 {};
+template <>
+struct R2<double> {
+  using type = double2;
+};
+template <>
+struct R2<float> {
+  using type = float2;
+};
+
+// One direction's 9 entry arrays as a raw buffer resource: voffset = idx*sizeof(R2)
+// in a VGPR, soffset = e*V*sizeof(R2) in an SGPR.
+template <typename R>
+struct DirBuf {
+  __amdgpu_buffer_rsrc_t rs;
+  uint32_t estride;  // bytes between entry arrays = V * sizeof(R2)
+};
+
+template <typename R>
+__device__ __forceinline__ DirBuf<R> dir_buf(const void* links, const Geo& g, int mu) {
+  const uint32_t es = g.V * (uint32_t)sizeof(typename R2<R>::type);
+  const char* base = (const char*)links + (size_t)mu * 9 * (size_t)es;
+  DirBuf<R> b;
+  b.rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(9u * es), (int)kRsrcWord3);
+  b.estride = es;
+  return b;
+}
+
+__device__ __forceinline__ void ld_entry(const DirBuf<double>& b, uint32_t voff, int e, Cx<double>& out) {
+  auto v = __builtin_amdgcn_raw_buffer_load_b128(b.rs, voff, (int)(e * b.estride), 0);
+  double2 d;
+  __builtin_memcpy(&d, &v, sizeof d);
+  out.re = d.x;
+  out.im = d.y;
+}
+
+__device__ __forceinline__ void ld_entry(const DirBuf<float>& b, uint32_t voff, int e, Cx<float>& out) {
+  auto v = __builtin_amdgcn_raw_buffer_load_b64(b.rs, voff, (int)(e * b.estride), 0);
+  float2 d;
+  __builtin_memcpy(&d, &v, sizeof d);
+  out.re = d.x;
+  out.im = d.y;
+}
+
+template <typename R>
+__device__ __forceinline__ M3<R> ld_link(const DirBuf<R>& b, uint32_t idx) {
+  M3<R> m;
+  const uint32_t voff = idx * (uint32_t)sizeof(typename R2<R>::type);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) ld_entry(b, voff, e, m.a[e]);
+  return m;
+}
+
+template <typename R>
+__device__ __forceinline__ void st_link(void* links, const Geo& g, int mu, uint32_t idx, const M3<R>& m) {
+  using T2 = typename R2<R>::type;
+  T2* p = (T2*)links + (size_t)mu * 9 * g.V + idx;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    T2 v;
+    v.x = m.a[e].re;
+    v.y = m.a[e].im;
+    p[(size_t)e * g.V] = v;
+  }
+}
+
+// ------------------------------------------------------------------ centre sector
+
+// Eq. (centre_element) written without arg(): for t = a + i b,
+//   n = 0  iff a > 0 and b^2 < 3 a^2          (|arg t| < pi/3)
+//   n = +1 iff b > 0 and (a <= 0 or b^2 > 3 a^2)  (arg t in (pi/3, pi))
+//   n = -1 iff b < 0 and (a <= 0 or b^2 > 3 a^2)  (arg t in (-pi, -pi/3))
+// and undefined on the boundaries and at t = 0.
+__device__ __forceinline__ int z3_sector(double a, double b) {
+  if (!(isfinite(a) && isfinite(b))) return kUndef;
+  const double a3 = 3.0 * a * a, b2 = b * b;
+  if (a > 0.0 && b2 < a3) return 0;
+  const bool outside = (a <= 0.0) || (b2 > a3);
+  if (b > 0.0 && outside) return 1;
+  if (b < 0.0 && outside) return -1;
+  return kUndef;
+}
+
+// The Z(3) element e^{2 pi i n/3} with the exact real part -1/2 for n = +-1.
+__device__ __forceinline__ Cx<double> z3_elem(int n) {
+  const double s = 0.86602540378443864676;  // sqrt(3)/2
+  if (n == 0) return cx<double>(1.0, 0.0);
+  return cx<double>(-0.5, n > 0 ? s : -s);
+}
+
+// ------------------------------------------------------------------ exponential
+
+// exp(X) for X traceless anti-Hermitian, as exp(iH) = f0 + f1 H + f2 H^2 with
+// H = -i X Hermitian traceless, c0 = det H, c1 = Tr H^2 / 2 (Cayley-Hamilton:
+// H^3 = c1 H + c0).  Coefficients f_j in FP64:
+//  * c1 < 0.5 (all eigenvalues below 0.82 in size): the Taylor series of
+//    exp(iH) reduced with H^3 = c1 H + c0, summed to order 20 (remainder below
+//    1e-19) -- no cancellation as c1 -> 0, where the closed form is 0/0;
+//  * otherwise the closed form of Morningstar & Peardon with theta, u, w and the
+//    symmetry f_j(-c0) = (-1)^j conj f_j(c0).
+struct CHCoef {
+  Cx<double> f0, f1, f2;
+};
+
+__device__ __forceinline__ CHCoef ch_coefficients(double c0, double c1) {
+  CHCoef r;
+  if (c1 < 0.5) {
+    // H^k = a_k + b_k H + c_k H^2; (a,b,c)_{k+1} = (c0 c_k, a_k + c1 c_k, b_k); with
+    // the 1/k! folded in.  i^k cycles through 1, i, -1, -i.
+    double a = 1.0, b = 0.0, c = 0.0;
+    double f0r = 1.0, f0i = 0.0, f1r = 0.0, f1i = 0.0, f2r = 0.0, f2i = 0.0;
+#pragma unroll
+    for (int k = 1; k <= 20; ++k) {
+      const double inv = 1.0 / (double)k;
+      const double na = c0 * c * inv;
+      const double nb = fma(c1, c, a) * inv;
+      const double nc = b * inv;
+      a = na;
+      b = nb;
+      c = nc;
+      switch (k & 3) {
+        case 0: f0r += a; f1r += b; f2r += c; break;
+        case 1: f0i += a; f1i += b; f2i += c; break;
+        case 2: f0r -= a; f1r -= b; f2r -= c; break;
+        default: f0i -= a; f1i -= b; f2i -= c; break;
+      }
+    }
+    r.f0 = cx<double>(f0r, f0i);
+    r.f1 = cx<double>(f1r, f1i);
+    r.f2 = cx<double>(f2r, f2i);
+    return r;
+  }
+  const bool neg = c0 < 0.0;
+  const double c0a = fabs(c0);
+  const double c0max = 2.0 * c1 / 3.0 * sqrt(c1 / 3.0);
+  double ratio = c0a / c0max;
+  ratio = ratio > 1.0 ? 1.0 : ratio;
+  const double theta = acos(ratio);
+  const double u = sqrt(c1 / 3.0) * cos(theta / 3.0);
+  const double w = sqrt(c1) * sin(theta / 3.0);
+  const double u2 = u * u, w2 = w * w;
+  double xi0;
+  if (fabs(w) < 0.05)
+    xi0 = 1.0 - w2 / 6.0 * (1.0 - w2 / 20.0 * (1.0 - w2 / 42.0));
+  else
+    xi0 = sin(w) / w;
+  const double cw = cos(w);
+  double s2u, c2u, su, cu;
+  sincos(2.0 * u, &s2u, &c2u);
+  sincos(u, &su, &cu);
+  // e^{-iu} * (p + i q)
+  auto emiu = [&](double p, double q) { return cx<double>(cu * p + su * q, cu * q - su * p); };
+  const Cx<double> t0 = emiu(8.0 * u2 * cw, 2.0 * u * (3.0 * u2 + w2) * xi0);
+  const Cx<double> t1 = emiu(2.0 * u * cw, -(3.0 * u2 - w2) * xi0);
+  const Cx<double> t2 = emiu(cw, 3.0 * u * xi0);
+  const double den = 1.0 / (9.0 * u2 - w2);
+  Cx<double> h0 = cx<double>((u2 - w2) * c2u + t0.re, (u2 - w2) * s2u + t0.im);
+  Cx<double> h1 = cx<double>(2.0 * u * c2u - t1.re, 2.0 * u * s2u - t1.im);
+  Cx<double> h2 = cx<double>(c2u - t2.re, s2u - t2.im);
+  r.f0 = cx<double>(h0.re * den, h0.im * den);
+  r.f1 = cx<double>(h1.re * den, h1.im * den);
+  r.f2 = cx<double>(h2.re * den, h2.im * den);
+  if (neg) {
+    r.f0 = cx<double>(r.f0.re, -r.f0.im);
+    r.f1 = cx<double>(-r.f1.re, r.f1.im);
+    r.f2 = cx<double>(r.f2.re, -r.f2.im);
+  }
+  return r;
+}
+
+// H = -i X for X anti-Hermitian: H_ij = (Im X_ij, -Re X_ij).  Returns c0, c1 in FP64.
+template <typename R>
+__device__ __forceinline__ void ch_invariants(const M3<R>& h, double& c0, double& c1) {
+  const double h00 = h.a[0].re, h11 = h.a[4].re, h22 = h.a[8].re;
+  const double x01r = h.a[1].re, x01i = h.a[1].im;
+  const double x02r = h.a[2].re, x02i = h.a[2].im;
+  const double x12r = h.a[5].re, x12i = h.a[5].im;
+  const double n01 = x01r * x01r + x01i * x01i;
+  const double n02 = x02r * x02r + x02i * x02i;
+  const double n12 = x12r * x12r + x12i * x12i;
+  c1 = 0.5 * (h00 * h00 + h11 * h11 + h22 * h22) + n01 + n02 + n12;
+  // det H = h00 h11 h22 + 2 Re(h01 h12 h20) - h00 |h12|^2 - h11 |h02|^2 - h22 |h01|^2
+  // with h20 = conj(h02)
+  const double pr = x01r * x12r - x01i * x12i;
+  const double pi = x01r * x12i + x01i * x12r;
+  const double re3 = pr * x02r + pi * x02i;
+  c0 = h00 * h11 * h22 + 2.0 * re3 - h00 * n12 - h11 * n02 - h22 * n01;
+}
+
+// ------------------------------------------------------------------ reunitarise
+
+// Gram-Schmidt on rows 0 and 1, row 2 = conj(row0 x row1): the nearest SU(3)
+// matrix to first order, exact structure for diagonal input.  FP64.
+__device__ __forceinline__ void reunitarise(M3<double>& u) {
+  double n0 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n0 += u.a[k].re * u.a[k].re + u.a[k].im * u.a[k].im;
+  const double i0 = 1.0 / sqrt(n0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    u.a[k].re *= i0;
+    u.a[k].im *= i0;
+  }
+  Cx<double> ip = cx<double>(0.0, 0.0);  // <r0, r1> = sum conj(r0_k) r1_k
+#pragma unroll
+  for (int k = 0; k < 3; ++k) cfma_c1(ip, u.a[k], u.a[3 + k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    // r1 -= ip * r0
+    u.a[3 + k].re -= ip.re * u.a[k].re - ip.im * u.a[k].im;
+    u.a[3 + k].im -= ip.re * u.a[k].im + ip.im * u.a[k].re;
+  }
+  double n1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n1 += u.a[3 + k].re * u.a[3 + k].re + u.a[3 + k].im * u.a[3 + k].im;
+  const double i1 = 1.0 / sqrt(n1);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    u.a[3 + k].re *= i1;
+    u.a[3 + k].im *= i1;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+    // (r0 x r1)_k = r0_k1 r1_k2 - r0_k2 r1_k1 ; row 2 = conj of that
+    const Cx<double>& a1 = u.a[k1];
+    const Cx<double>& a2 = u.a[k2];
+    const Cx<double>& b1 = u.a[3 + k1];
+    const Cx<double>& b2 = u.a[3 + k2];
+    const double re = (a1.re * b2.re - a1.im * b2.im) - (a2.re * b1.re - a2.im * b1.im);
+    const double im = (a1.re * b2.im + a1.im * b2.re) - (a2.re * b1.im + a2.im * b1.re);
+    u.a[6 + k] = cx<double>(re, -im);
+  }
+}
+
+}  // namespace vsm

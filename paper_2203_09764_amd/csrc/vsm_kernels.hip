@@ -1,0 +1,79 @@
+// vsm_kernels.hip -- precision dispatch of the kernel launchers, and the small
+// kernels that do not depend on the precision.
+#include "vsm_launch.h"
+
+namespace vsm {
+
+template <typename R>
+void launch_set_links_t(const Geo&, const void*, void*, hipStream_t);
+template <typename R>
+void launch_get_links_t(const Geo&, const void*, void*, hipStream_t);
+template <typename R>
+void launch_load_z3_t(const Geo&, const int8_t*, void*, hipStream_t);
+template <typename R>
+void launch_centrifuge_t(const Geo&, const int8_t*, const int8_t*, double, void*, int32_t*, hipStream_t);
+template <typename R>
+void launch_gauge_t(const Geo&, void*, const void*, hipStream_t);
+template <typename R>
+void launch_update_t(const Geo&, const void*, void*, const int8_t*, const void*, const UpdParams&, int,
+                     int, int, unsigned long long*, hipStream_t);
+template <typename R>
+void launch_measure_t(const Geo&, const void*, const int8_t*, void*, int8_t*, unsigned long long*,
+                      VsmStatsDev*, long long, hipStream_t);
+
+// Clears n 64-bit counters (a kernel rather than a memset, so that the call can
+// sit inside a captured graph).
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+void launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, p, n);
+}
+
+void launch_set_links(int prec, const Geo& g, const void* canon, void* links, hipStream_t st) {
+  if (prec == 0) launch_set_links_t<double>(g, canon, links, st);
+  else launch_set_links_t<float>(g, canon, links, st);
+}
+
+void launch_get_links(int prec, const Geo& g, const void* links, void* canon, hipStream_t st) {
+  if (prec == 0) launch_get_links_t<double>(g, links, canon, st);
+  else launch_get_links_t<float>(g, links, canon, st);
+}
+
+void launch_load_z3(int prec, const Geo& g, const int8_t* z3, void* links, hipStream_t st) {
+  if (prec == 0) launch_load_z3_t<double>(g, z3, links, st);
+  else launch_load_z3_t<float>(g, z3, links, st);
+}
+
+void launch_centrifuge(int prec, const Geo& g, const int8_t* z3, const int8_t* pair, double omega,
+                       void* links, int32_t* m_out, hipStream_t st) {
+  if (prec == 0) launch_centrifuge_t<double>(g, z3, pair, omega, links, m_out, st);
+  else launch_centrifuge_t<float>(g, z3, pair, omega, links, m_out, st);
+}
+
+void launch_gauge(int prec, const Geo& g, void* links, const void* gauge, hipStream_t st) {
+  if (prec == 0) launch_gauge_t<double>(g, links, gauge, st);
+  else launch_gauge_t<float>(g, links, gauge, st);
+}
+
+void launch_update(int prec, const Geo& g, const void* src, void* dst, const int8_t* z3,
+                   const void* gauge, const UpdParams& p, int mu, int colour, int jacobi,
+                   unsigned long long* rej, hipStream_t st) {
+  if (prec == 0) launch_update_t<double>(g, src, dst, z3, gauge, p, mu, colour, jacobi, rej, st);
+  else launch_update_t<float>(g, src, dst, z3, gauge, p, mu, colour, jacobi, rej, st);
+}
+
+// Block partials written by the measurement kernel: 10 eight-byte fields.
+uint32_t measure_blocks(const Geo& g) { return (g.V + 255u) / 256u; }
+size_t partial_bytes() { return 80; }
+
+void launch_measure(int prec, const Geo& g, const void* links, const int8_t* z3, void* partials,
+                    int8_t* flux, unsigned long long* rej, VsmStatsDev* out, long long sweep,
+                    hipStream_t st) {
+  if (prec == 0) launch_measure_t<double>(g, links, z3, partials, flux, rej, out, sweep, st);
+  else launch_measure_t<float>(g, links, z3, partials, flux, rej, out, sweep, st);
+}
+
+}  // namespace vsm

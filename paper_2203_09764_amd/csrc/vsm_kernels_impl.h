@@ -1,0 +1,786 @@
+// vsm_kernels_impl.h -- HIP kernels of the vortex-field smoothing path (gfx950).
+// Included once per precision by vsm_k_f64.hip and vsm_k_f32.hip.
+//
+// Kernels (all launched by vsm_api.hip on the caller's stream):
+//   k_set_links / k_get_links : canonical complex128 [4][V][3][3] <-> internal layout
+//   k_load_z3                 : Z(3) charges -> centre-element links (Eq. centre_project)
+//   k_centrifuge              : centrifuge preconditioning (Sec. IV)
+//   k_gauge                   : U -> G(x) U G^dagger(x + mu) (Sec. V.C)
+//   k_update<R, MU, OI, UPD>  : one annealing subset or one smearing step of
+//                               stout (Eq. stout) or MaxReTr (Sec. III) updates
+//                               with the vortex-preserving test (Sec. VI)
+//   k_measure / k_finalize    : plaquette, Wilson action, vortex flux (Sec. I, V.A)
+#pragma once
+
+#include "vsm_device.h"
+#include "vsm_launch.h"
+
+namespace vsm {
+
+// ------------------------------------------------------------------ layout
+
+template <typename R>
+__global__ void k_set_links(Geo g, const double2* __restrict__ canon, void* links) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 4u * g.V) return;
+  const int mu = (int)(tid / g.V);
+  const uint32_t s = tid - (uint32_t)mu * g.V;
+  int c[4];
+  coords_of_canonical(g, s, c);
+  const uint32_t idx = blocked_index(g, c);
+  const double2* src = canon + ((size_t)mu * g.V + s) * 9;
+  M3<R> m;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) m.a[e] = cx<R>((R)src[e].x, (R)src[e].y);
+  st_link<R>(links, g, mu, idx, m);
+}
+
+template <typename R>
+__global__ void k_get_links(Geo g, const void* links, double2* __restrict__ canon) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 4u * g.V) return;
+  const int mu = (int)(tid / g.V);
+  const uint32_t s = tid - (uint32_t)mu * g.V;
+  int c[4];
+  coords_of_canonical(g, s, c);
+  const uint32_t idx = blocked_index(g, c);
+  const DirBuf<R> b = dir_buf<R>(links, g, mu);
+  const M3<R> m = ld_link<R>(b, idx);
+  double2* dst = canon + ((size_t)mu * g.V + s) * 9;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) dst[e] = make_double2((double)m.a[e].re, (double)m.a[e].im);
+}
+
+// ------------------------------------------------------------------ ingest
+
+template <typename R>
+__global__ void k_load_z3(Geo g, const int8_t* __restrict__ z3, void* links) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 4u * g.V) return;
+  const int mu = (int)(tid / g.V);
+  const uint32_t s = tid - (uint32_t)mu * g.V;
+  int c[4];
+  coords_of_canonical(g, s, c);
+  const Cx<double> z = z3_elem(z3[tid]);
+  M3<R> m = mzero<R>();
+  m.a[0] = m.a[4] = m.a[8] = cx<R>((R)z.re, (R)z.im);
+  st_link<R>(links, g, mu, blocked_index(g, c), m);
+}
+
+// ------------------------------------------------------------------ centrifuge
+
+// Sec. IV: with lambda = 2 pi n/3 and the staple phase sigma = 2 pi m/18,
+//   lambda^j = lambda + omega (sigma - lambda),  lambda^k = lambda - omega (sigma - lambda),
+// i.e. e^{i lambda^j} = z(n) e^{+i d}, e^{i lambda^k} = z(n) e^{-i d} with
+// d = omega (2 pi / 18) (m - 6 n), and the third phase stays lambda.  m is the
+// exact integer sum of the 18 neighbouring charges of the six staples.
+template <typename R>
+__global__ void k_centrifuge(Geo g, const int8_t* __restrict__ z3, const int8_t* __restrict__ pair,
+                             double omega, void* links, int32_t* __restrict__ m_out) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 4u * g.V) return;
+  const int mu = (int)(tid / g.V);
+  const uint32_t s = tid - (uint32_t)mu * g.V;
+  int c[4];
+  coords_of_canonical(g, s, c);
+  auto nat = [&](int d, int dmu, int dnu, int nu) -> int {
+    int e[4] = {c[0], c[1], c[2], c[3]};
+    e[mu] += dmu;
+    e[nu] += dnu;
+    if (e[mu] >= g.L[mu]) e[mu] -= g.L[mu];
+    if (e[nu] < 0) e[nu] += g.L[nu];
+    if (e[nu] >= g.L[nu]) e[nu] -= g.L[nu];
+    return (int)z3[(size_t)d * g.V + canonical_index(g, e)];
+  };
+  int m = 0;
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) continue;
+    m += nat(nu, 0, 0, nu) + nat(mu, 0, 1, nu) - nat(nu, 1, 0, nu);    // upper staple
+    m += -nat(nu, 0, -1, nu) + nat(mu, 0, -1, nu) + nat(nu, 1, -1, nu);  // lower staple
+  }
+  const int n = z3[tid];
+  const double d = omega * (2.0 * 3.14159265358979323846 / 18.0) * (double)(m - 6 * n);
+  double sd, cd;
+  sincos(d, &sd, &cd);
+  const Cx<double> z = z3_elem(n);
+  const Cx<double> zp = cx<double>(z.re * cd - z.im * sd, z.re * sd + z.im * cd);
+  const Cx<double> zm = cx<double>(z.re * cd + z.im * sd, z.im * cd - z.re * sd);
+  const int j = pair[tid];
+  const int k = (j + 1) % 3;
+  M3<R> u = mzero<R>();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const Cx<double> v = (i == j) ? zp : ((i == k) ? zm : z);
+    u.a[4 * i] = cx<R>((R)v.re, (R)v.im);
+  }
+  st_link<R>(links, g, mu, blocked_index(g, c), u);
+  if (m_out) m_out[tid] = m;
+}
+
+// ------------------------------------------------------------------ gauge transform
+
+template <typename R>
+__global__ void k_gauge(Geo g, void* links, const double2* __restrict__ gauge) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 4u * g.V) return;
+  const int mu = (int)(tid / g.V);
+  const uint32_t s = tid - (uint32_t)mu * g.V;
+  int c[4];
+  coords_of_canonical(g, s, c);
+  const uint32_t idx = blocked_index(g, c);
+  int cp[4] = {c[0], c[1], c[2], c[3]};
+  cp[mu] = (cp[mu] + 1) % g.L[mu];
+  const uint32_t sp = canonical_index(g, cp);
+  M3<double> G, Gp;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    G.a[e] = cx<double>(gauge[(size_t)s * 9 + e].x, gauge[(size_t)s * 9 + e].y);
+    Gp.a[e] = cx<double>(gauge[(size_t)sp * 9 + e].x, gauge[(size_t)sp * 9 + e].y);
+  }
+  const DirBuf<R> b = dir_buf<R>(links, g, mu);
+  const M3<double> u = mconvert<double>(ld_link<R>(b, idx));
+  const M3<double> r = mul_nd(mul_nn(G, u), Gp);
+  st_link<R>(links, g, mu, idx, mconvert<R>(r));
+}
+
+// ------------------------------------------------------------------ staples
+
+// Staple paths as chains of link products (Eq. plaq_staples and the
+// over-improvement diagrams).  A chain multiplies a running product by one link
+// (or its adjoint) at a time, so that only Sigma, the running product, the link
+// being multiplied and the next link in flight are live.  The compiler-only
+// memory fence after every load keeps a link that several paths share from
+// being loaded once and held across the whole staple (36 VGPRs per matrix in
+// FP64): it is reloaded from cache instead, and the load of the next link can
+// still overlap the current product.
+__device__ __forceinline__ void load_fence() { asm volatile("" ::: "memory"); }
+
+template <typename R, bool D>
+__device__ __forceinline__ void chain_step(M3<R>& run, const DirBuf<R>& b, uint32_t i) {
+  const M3<R> m = ld_link(b, i);
+  load_fence();
+  run = D ? mul_nd(run, m) : mul_nn(run, m);
+}
+
+template <typename R, bool D0, bool D1>
+__device__ __forceinline__ M3<R> chain_start(const DirBuf<R>& b0, uint32_t i0, const DirBuf<R>& b1,
+                                             uint32_t i1) {
+  const M3<R> x = ld_link(b0, i0);
+  load_fence();
+  const M3<R> y = ld_link(b1, i1);
+  load_fence();
+  M3<R> r;
+  if (!D0 && !D1) r = mul_nn(x, y);
+  if (!D0 && D1) r = mul_nd(x, y);
+  if (D0 && !D1) r = mul_dn(x, y);
+  if (D0 && D1) r = mul_nn(y, x);  // x^dag y^dag = (y x)^dag, adjointed below
+  if (D0 && D1) {
+    M3<R> t;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) t.a[3 * i + j] = cx<R>(r.a[3 * j + i].re, -r.a[3 * j + i].im);
+    r = t;
+  }
+  return r;
+}
+
+// Neighbour offsets of site x (blocked index deltas) along mu and one nu.
+struct Nb {
+  int mm, mp, mp2;            // -mu, +mu, +2mu
+  int nm2, nm, np, np2;       // -2nu, -nu, +nu, +2nu
+};
+
+// Sigma contribution of one nu and one orientation.  Paths from x to x + mu
+// (a step -d multiplies the adjoint of the link it walks back along):
+//   +nu: plaquette  +nu +mu -nu          : U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
+//        1x2        +nu +nu +mu -nu -nu  : U_nu(x) U_nu(x+nu) U_mu(x+2nu) U_nu(x+mu+nu)^dag U_nu(x+mu)^dag
+//        2x1 left   +nu +mu +mu -nu -mu  : U_nu(x) U_mu(x+nu) U_mu(x+mu+nu) U_nu(x+2mu)^dag U_mu(x+mu)^dag
+//        2x1 middle -mu +nu +mu +mu -nu  : U_mu(x-mu)^dag U_nu(x-mu) U_mu(x-mu+nu) U_mu(x+nu) U_nu(x+mu)^dag
+//   -nu: the same paths with nu reversed.
+// Weights: (5 - 2 eps)/3 for the plaquette staple, (eps - 1)/(12 u0^2) for rectangles.
+template <typename R, bool OI, bool UP>
+__device__ __forceinline__ void staple_dir(M3<R>& S, const DirBuf<R>& bm, const DirBuf<R>& bn,
+                                           uint32_t x, const Nb& o, R cp, R cr) {
+  if (UP) {
+    M3<R> w = chain_start<R, false, false>(bn, x, bm, x + o.np);
+    chain_step<R, true>(w, bn, x + o.mp);
+    maxpy(S, cp, w);
+    if (!OI) return;
+    w = chain_start<R, false, false>(bn, x, bn, x + o.np);
+    chain_step<R, false>(w, bm, x + o.np2);
+    chain_step<R, true>(w, bn, x + o.mp + o.np);
+    chain_step<R, true>(w, bn, x + o.mp);
+    maxpy(S, cr, w);
+    w = chain_start<R, false, false>(bn, x, bm, x + o.np);
+    chain_step<R, false>(w, bm, x + o.mp + o.np);
+    chain_step<R, true>(w, bn, x + o.mp2);
+    chain_step<R, true>(w, bm, x + o.mp);
+    maxpy(S, cr, w);
+    w = chain_start<R, true, false>(bm, x + o.mm, bn, x + o.mm);
+    chain_step<R, false>(w, bm, x + o.mm + o.np);
+    chain_step<R, false>(w, bm, x + o.np);
+    chain_step<R, true>(w, bn, x + o.mp);
+    maxpy(S, cr, w);
+  } else {
+    M3<R> w = chain_start<R, true, false>(bn, x + o.nm, bm, x + o.nm);
+    chain_step<R, false>(w, bn, x + o.nm + o.mp);
+    maxpy(S, cp, w);
+    if (!OI) return;
+    w = chain_start<R, true, true>(bn, x + o.nm, bn, x + o.nm2);
+    chain_step<R, false>(w, bm, x + o.nm2);
+    chain_step<R, false>(w, bn, x + o.nm2 + o.mp);
+    chain_step<R, false>(w, bn, x + o.nm + o.mp);
+    maxpy(S, cr, w);
+    w = chain_start<R, true, false>(bn, x + o.nm, bm, x + o.nm);
+    chain_step<R, false>(w, bm, x + o.nm + o.mp);
+    chain_step<R, false>(w, bn, x + o.nm + o.mp2);
+    chain_step<R, true>(w, bm, x + o.mp);
+    maxpy(S, cr, w);
+    w = chain_start<R, true, true>(bm, x + o.mm, bn, x + o.mm + o.nm);
+    chain_step<R, false>(w, bm, x + o.mm + o.nm);
+    chain_step<R, false>(w, bm, x + o.nm);
+    chain_step<R, false>(w, bn, x + o.nm + o.mp);
+    maxpy(S, cr, w);
+  }
+}
+
+// ------------------------------------------------------------------ updates
+
+// Stout (Eq. stout, Eq. generator): Omega = Sigma U^dag, Q its traceless
+// anti-Hermitian part (diagonal from differences so that an Omega proportional
+// to 1 gives exactly Q = 0), X = rho Q, U' = exp(X) U via Cayley-Hamilton with
+// FP64 coefficients, then FP64 reunitarisation.  Q = 0 returns U unchanged.
+template <typename R>
+__device__ __forceinline__ bool stout_candidate(const M3<R>& S, const M3<R>& U, double rho,
+                                                M3<double>& out) {
+  const M3<R> om = mul_nd(S, U);
+  // A = (Omega - Omega^dag)/2 ; Q_ij = A_ij off the diagonal; diagonal A_ii is i*a_i
+  const R a0 = om.a[0].im, a1 = om.a[4].im, a2 = om.a[8].im;
+  const R q0 = ((a0 - a1) + (a0 - a2)) / R(3);
+  const R q1 = ((a1 - a0) + (a1 - a2)) / R(3);
+  const R q2 = ((a2 - a0) + (a2 - a1)) / R(3);
+  // H = -i rho Q: H_ii = rho q_i ; H_ij = -i rho A_ij with A_ij = (om_ij - conj om_ji)/2
+  M3<R> H;
+  const R r = (R)rho;
+  H.a[0] = cx<R>(r * q0, R(0));
+  H.a[4] = cx<R>(r * q1, R(0));
+  H.a[8] = cx<R>(r * q2, R(0));
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 3; ++j) {
+      const R ar = R(0.5) * (om.a[3 * i + j].re - om.a[3 * j + i].re);
+      const R ai = R(0.5) * (om.a[3 * i + j].im + om.a[3 * j + i].im);
+      // -i (ar + i ai) = ai - i ar
+      H.a[3 * i + j] = cx<R>(r * ai, -r * ar);
+      H.a[3 * j + i] = cx<R>(r * ai, r * ar);
+    }
+  double c0, c1;
+  ch_invariants(H, c0, c1);
+  if (c1 == 0.0) return false;
+  const CHCoef f = ch_coefficients(c0, c1);
+  // E = f0 + f1 H + f2 H^2 in the working precision
+  const M3<R> H2 = mul_nn(H, H);
+  M3<R> E;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    Cx<R> v = cx<R>(R(0), R(0));
+    cfma(v, cx<R>((R)f.f1.re, (R)f.f1.im), H.a[e]);
+    cfma(v, cx<R>((R)f.f2.re, (R)f.f2.im), H2.a[e]);
+    E.a[e] = v;
+  }
+  E.a[0].re += (R)f.f0.re;
+  E.a[0].im += (R)f.f0.im;
+  E.a[4].re += (R)f.f0.re;
+  E.a[4].im += (R)f.f0.im;
+  E.a[8].re += (R)f.f0.re;
+  E.a[8].im += (R)f.f0.im;
+  out = mconvert<double>(mul_nn(E, U));
+  reunitarise(out);
+  return true;
+}
+
+// MaxReTr (Eq. maxReTr, def_L1, def_T1): V = (1 - alpha) U + (alpha/6) Sigma,
+// L = U V^dag; for loops x subgroups (0,1), (1,2), (0,2): T from L's 2x2 block,
+// k = sqrt(det T), T^c = T^dag / k, U <- T^c U and L <- T^c L.  A hit with
+// k <= 1e-12 (|L|_F + 1) is skipped (k = 0 leaves the hit undefined).  FP64.
+template <typename R>
+__device__ __forceinline__ bool maxretr_candidate(const M3<R>& S, const M3<R>& U0, double alpha,
+                                                  int loops, M3<double>& out) {
+  M3<double> U = mconvert<double>(U0);
+  M3<double> Vb;
+  const M3<double> Sd = mconvert<double>(S);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    Vb.a[e].re = (1.0 - alpha) * U.a[e].re + alpha / 6.0 * Sd.a[e].re;
+    Vb.a[e].im = (1.0 - alpha) * U.a[e].im + alpha / 6.0 * Sd.a[e].im;
+  }
+  M3<double> L = mul_nd(U, Vb);
+  double lf = 0.0;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) lf += L.a[e].re * L.a[e].re + L.a[e].im * L.a[e].im;
+  lf = sqrt(lf);
+  const double thr = 1e-12 * (lf + 1.0);
+  bool moved = false;
+  for (int it = 0; it < loops; ++it) {
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+      const int p = (h == 1) ? 1 : 0;
+      const int q = (h == 0) ? 1 : 2;
+      const Cx<double> Lpp = L.a[4 * p], Lqq = L.a[4 * q], Lpq = L.a[3 * p + q], Lqp = L.a[3 * q + p];
+      // T = [[a, b], [-conj b, conj a]] with a = (Lpp + conj Lqq)/2, b = (Lpq - conj Lqp)/2
+      const double ar = 0.5 * (Lpp.re + Lqq.re), ai = 0.5 * (Lpp.im - Lqq.im);
+      const double br = 0.5 * (Lpq.re - Lqp.re), bi = 0.5 * (Lpq.im + Lqp.im);
+      const double det = ar * ar + ai * ai + br * br + bi * bi;
+      const double k = sqrt(det);
+      if (!(k > thr)) continue;
+      const double ik = 1.0 / k;
+      // T^c = T^dag / k = [[conj a, -b], [conj b, a]] / k
+      const Cx<double> t00 = cx<double>(ar * ik, -ai * ik), t01 = cx<double>(-br * ik, -bi * ik);
+      const Cx<double> t10 = cx<double>(br * ik, -bi * ik), t11 = cx<double>(ar * ik, ai * ik);
+#pragma unroll
+      for (int col = 0; col < 3; ++col) {
+        Cx<double> up = cx<double>(0.0, 0.0), uq = cx<double>(0.0, 0.0);
+        cfma(up, t00, U.a[3 * p + col]);
+        cfma(up, t01, U.a[3 * q + col]);
+        cfma(uq, t10, U.a[3 * p + col]);
+        cfma(uq, t11, U.a[3 * q + col]);
+        U.a[3 * p + col] = up;
+        U.a[3 * q + col] = uq;
+        Cx<double> lp = cx<double>(0.0, 0.0), lq = cx<double>(0.0, 0.0);
+        cfma(lp, t00, L.a[3 * p + col]);
+        cfma(lp, t01, L.a[3 * q + col]);
+        cfma(lq, t10, L.a[3 * p + col]);
+        cfma(lq, t11, L.a[3 * q + col]);
+        L.a[3 * p + col] = lp;
+        L.a[3 * q + col] = lq;
+      }
+      moved = true;
+    }
+  }
+  out = U;
+  return moved;
+}
+
+// Tr[G^dagger(x) U G(x + mu)]: the trace the vortex-preservation test projects
+// when the field lives in the random gauge G (Sec. VI).
+__device__ __noinline__ Cx<double> gauge_undone_trace(const double2* __restrict__ gauge, uint32_t s0,
+                                                     uint32_t s1, M3<double> u) {
+  M3<double> G, Gp;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    G.a[e] = cx<double>(gauge[(size_t)s0 * 9 + e].x, gauge[(size_t)s0 * 9 + e].y);
+    Gp.a[e] = cx<double>(gauge[(size_t)s1 * 9 + e].x, gauge[(size_t)s1 * 9 + e].y);
+  }
+  return mtrace(mul_nn(mul_dn(G, u), Gp));
+}
+
+// The thread's link of an annealing subset (Sec. III.A masking).  Subset c of
+// direction mu holds the sites with (2 x_mu + sum_{nu != mu} x_nu) mod 4 = c.
+//   mu != 0: in every row (y, z, t) the subset has one residue q = x mod 4, so
+//            thread t maps to j = t (all x >> 2 of all rows) in sublattice q(row);
+//   mu == 0: only rows with y + z + t of the parity of c take part, with the two
+//            residues q = h, h + 2, h = ((c - y - z - t) mod 4) / 2.
+template <int MU>
+__device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t, int c[4]) {
+  if (MU != 0) {
+    const uint32_t xi = t % (uint32_t)g.Xq;
+    uint32_t r = t / (uint32_t)g.Xq;
+    c[1] = (int)(r % (uint32_t)g.L[1]);
+    r /= (uint32_t)g.L[1];
+    c[2] = (int)(r % (uint32_t)g.L[2]);
+    c[3] = (int)(r / (uint32_t)g.L[2]);
+    int rest = 2 * c[MU];
+#pragma unroll
+    for (int d = 1; d < 4; ++d)
+      if (d != MU) rest += c[d];
+    const int q = (colour - rest) & 3;
+    c[0] = (int)(4 * xi) + q;
+  } else {
+    const uint32_t two = 2u * (uint32_t)g.Xq;
+    const uint32_t k = t / two;
+    const uint32_t rem = t - k * two;
+    const uint32_t which = rem / (uint32_t)g.Xq;
+    const uint32_t xi = rem - which * (uint32_t)g.Xq;
+    const uint32_t half = (uint32_t)g.L[1] / 2u;
+    const uint32_t yh = k % half;
+    const uint32_t zt = k / half;
+    c[2] = (int)(zt % (uint32_t)g.L[2]);
+    c[3] = (int)(zt / (uint32_t)g.L[2]);
+    c[1] = (int)(2 * yh) + ((colour - c[2] - c[3]) & 1);
+    const int S = c[1] + c[2] + c[3];
+    const int h = ((colour - S) & 3) >> 1;
+    c[0] = (int)(4 * xi) + h + 2 * (int)which;
+  }
+}
+
+// One update step for direction MU.  jacobi = 0: the annealing subset `colour`,
+// in place (src == dst).  jacobi = 1: every link of direction MU from src into
+// dst (smearing).  UPD = 0 stout, 1 MaxReTr.  With vp, a candidate is kept only
+// if its centre sector (after undoing the gauge transform, when one is given)
+// equals the original charge; rejections are counted per wave into *rejected.
+template <typename R, int MU, bool OI, int UPD>
+__global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* dst,
+                                                const int8_t* __restrict__ z3,
+                                                const double2* __restrict__ gauge, UpdParams p,
+                                                int colour, int jacobi, uint32_t nthreads,
+                                                unsigned long long* __restrict__ rejected) {
+  // XCD-aware block order: consecutive hardware blocks go round-robin to the 8
+  // XCDs; give each XCD one contiguous range of the lattice for L2 reuse.
+  uint32_t b = blockIdx.x;
+  const uint32_t nb = gridDim.x;
+  if ((nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
+  const uint32_t t = b * blockDim.x + threadIdx.x;
+  const bool active = t < nthreads;
+  int c[4] = {0, 0, 0, 0};
+  if (active) {
+    if (jacobi)
+      coords_of_blocked(g, t, c);
+    else
+      subset_site<MU>(g, colour, t, c);
+  }
+  bool rej = false;
+  if (active) {
+    const uint32_t x = blocked_index(g, c);
+    const R cp = (R)p.cp, cr = (R)p.cr;
+    const DirBuf<R> bm = dir_buf<R>(src, g, MU);
+    M3<R> S = mzero<R>();
+#pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+      if (nu == MU) continue;
+      Nb o;
+      o.mm = delta(g, MU, c[MU], -1);
+      o.mp = delta(g, MU, c[MU], 1);
+      o.mp2 = delta(g, MU, c[MU], 2);
+      o.nm2 = delta(g, nu, c[nu], -2);
+      o.nm = delta(g, nu, c[nu], -1);
+      o.np = delta(g, nu, c[nu], 1);
+      o.np2 = delta(g, nu, c[nu], 2);
+      const DirBuf<R> bn = dir_buf<R>(src, g, nu);
+      staple_dir<R, OI, true>(S, bm, bn, x, o, cp, cr);
+      staple_dir<R, OI, false>(S, bm, bn, x, o, cp, cr);
+    }
+    const M3<R> U = ld_link(bm, x);
+    M3<double> cand;
+    bool moved;
+    if (UPD == 0)
+      moved = stout_candidate<R>(S, U, p.rho, cand);
+    else
+      moved = maxretr_candidate<R>(S, U, p.alpha, p.loops, cand);
+    const M3<R> cr_ = mconvert<R>(cand);
+    bool accept = moved;
+    if (moved && p.vp) {
+      // sector of the stored (rounded) candidate, evaluated in FP64
+      Cx<double> tr;
+      if (gauge) {
+        int cp1[4] = {c[0], c[1], c[2], c[3]};
+        cp1[MU] = (cp1[MU] + 1 == g.L[MU]) ? 0 : cp1[MU] + 1;
+        tr = gauge_undone_trace(gauge, canonical_index(g, c), canonical_index(g, cp1), mconvert<double>(cr_));
+      } else {
+        tr = mtrace(mconvert<double>(cr_));
+      }
+      const int n0 = z3[(size_t)MU * g.V + canonical_index(g, c)];
+      accept = (z3_sector(tr.re, tr.im) == n0);
+    }
+    rej = moved && !accept;
+    if (jacobi || accept) {
+      M3<R> outl;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        outl.a[e].re = accept ? cr_.a[e].re : U.a[e].re;
+        outl.a[e].im = accept ? cr_.a[e].im : U.a[e].im;
+      }
+      st_link<R>(dst, g, MU, x, outl);
+    }
+  }
+  if (rejected) {
+    const unsigned long long m = __ballot(rej);
+    if ((threadIdx.x & 63u) == 0u && m) atomicAdd(rejected, (unsigned long long)__popcll(m));
+  }
+}
+
+// ------------------------------------------------------------------ measurement
+
+// Neumaier/TwoSum accumulation of a double.
+struct KSum {
+  double s, c;
+};
+__device__ __forceinline__ void kadd(KSum& k, double v) {
+  const double t = k.s + v;
+  if (fabs(k.s) >= fabs(v))
+    k.c += (k.s - t) + v;
+  else
+    k.c += (v - t) + k.s;
+  k.s = t;
+}
+__device__ __forceinline__ void kmerge(KSum& k, const KSum& o) {
+  kadd(k, o.s);
+  k.c += o.c;
+}
+
+struct Partial {  // 80 bytes; partial_bytes() in vsm_kernels.hip must match
+  double plaq_s, plaq_c, act_s, act_c, max_unit, pad;
+  long long mism, undef, nonfin, pad2;
+};
+static_assert(sizeof(Partial) == 80, "partial record size is part of the workspace layout");
+
+__device__ __forceinline__ int link_sector(const M3<double>& u) {
+  const Cx<double> t = mtrace(u);
+  return z3_sector(t.re, t.im);
+}
+
+// Per site: the six plaquettes P_{mu nu}(x), mu < nu (Sec. I), summed as
+// Re Tr P and Re Tr[1 - P] (Sec. V.A); the sectors of the four links at x;
+// the vortex flux of every plaquette from the link sectors compared with the
+// flux of the original charges; unitarity and finiteness of the own links.
+// Block partials go to fixed slots; k_finalize sums them in a fixed order, so
+// the result does not depend on the scheduling.
+template <typename R>
+__global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const int8_t* __restrict__ z3,
+                                                 Partial* __restrict__ part, int8_t* __restrict__ flux) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  KSum kp = {0.0, 0.0}, ka = {0.0, 0.0};
+  double maxu = 0.0;
+  long long mism = 0, undef = 0, nonfin = 0;
+  if (s < g.V) {
+    int c[4];
+    coords_of_canonical(g, s, c);
+    const uint32_t x = blocked_index(g, c);
+    // sectors and original charges of the four links at x, one byte each
+    uint32_t secb = 0, n0b = 0;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      const M3<double> U = mconvert<double>(ld_link(dir_buf<R>(links, g, mu), x));
+      const int sc = link_sector(U);
+      secb |= (uint32_t)(sc & 0xff) << (8 * mu);
+      n0b |= (uint32_t)(z3[(size_t)mu * g.V + s] & 0xff) << (8 * mu);
+      bool fin = true;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) fin = fin && isfinite(U.a[e].re) && isfinite(U.a[e].im);
+      if (!fin) ++nonfin;
+      if (sc == kUndef) ++undef;
+      const M3<double> uu = mul_dn(U, U);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        const double dr = uu.a[e].re - ((e % 4 == 0) ? 1.0 : 0.0);
+        const double dv = sqrt(dr * dr + uu.a[e].im * uu.a[e].im);
+        maxu = fmax(maxu, dv);
+      }
+    }
+    auto byte_at = [](uint32_t w, int i) { return (int)(int8_t)((w >> (8 * i)) & 0xffu); };
+#pragma unroll 1
+    for (int plane = 0; plane < 6; ++plane) {
+      // planes 01, 02, 03, 12, 13, 23
+      const int mu = plane < 3 ? 0 : (plane < 5 ? 1 : 2);
+      const int nu = plane < 3 ? plane + 1 : (plane < 5 ? plane - 1 : 3);
+      int cm[4] = {c[0], c[1], c[2], c[3]};
+      cm[mu] = (cm[mu] + 1 == g.L[mu]) ? 0 : cm[mu] + 1;
+      int cn[4] = {c[0], c[1], c[2], c[3]};
+      cn[nu] = (cn[nu] + 1 == g.L[nu]) ? 0 : cn[nu] + 1;
+      const DirBuf<R> bmu = dir_buf<R>(links, g, mu), bnu = dir_buf<R>(links, g, nu);
+      const M3<double> A = mconvert<double>(ld_link(bmu, x));
+      load_fence();
+      const M3<double> B = mconvert<double>(ld_link(bnu, blocked_index(g, cm)));
+      load_fence();
+      const int sb = link_sector(B);
+      M3<double> P = mul_nn(A, B);
+      const M3<double> Cm = mconvert<double>(ld_link(bmu, blocked_index(g, cn)));
+      load_fence();
+      const int sc = link_sector(Cm);
+      P = mul_nd(P, Cm);
+      P = mul_nd(P, mconvert<double>(ld_link(bnu, x)));
+      load_fence();
+      const double rt = P.a[0].re + P.a[4].re + P.a[8].re;
+      const double ra = (1.0 - P.a[0].re) + (1.0 - P.a[4].re) + (1.0 - P.a[8].re);
+      kadd(kp, rt);
+      kadd(ka, ra);
+      const int smu = byte_at(secb, mu), snu = byte_at(secb, nu);
+      const int o = byte_at(n0b, mu) + (int)z3[(size_t)nu * g.V + canonical_index(g, cm)] -
+                    (int)z3[(size_t)mu * g.V + canonical_index(g, cn)] - byte_at(n0b, nu);
+      const int orig = ((o % 3) + 3) % 3;
+      int pv;
+      if (smu == kUndef || sb == kUndef || sc == kUndef || snu == kUndef) {
+        ++mism;
+        pv = kUndef;
+      } else {
+        const int r = (((smu + sb - sc - snu) % 3) + 3) % 3;
+        if (r != orig) ++mism;
+        pv = (r == 2) ? -1 : r;
+      }
+      if (flux) flux[(size_t)plane * g.V + s] = (int8_t)pv;
+    }
+  }
+  // wave reduction (fixed butterfly), then a fixed-order pass over the 4 waves
+  for (int off = 32; off > 0; off >>= 1) {
+    KSum op = {__shfl_xor(kp.s, off), __shfl_xor(kp.c, off)};
+    KSum oa = {__shfl_xor(ka.s, off), __shfl_xor(ka.c, off)};
+    kmerge(kp, op);
+    kmerge(ka, oa);
+    maxu = fmax(maxu, __shfl_xor(maxu, off));
+    mism += __shfl_xor(mism, off);
+    undef += __shfl_xor(undef, off);
+    nonfin += __shfl_xor(nonfin, off);
+  }
+  __shared__ Partial w[4];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    w[wave] = Partial{kp.s, kp.c, ka.s, ka.c, maxu, 0.0, mism, undef, nonfin, 0};
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Partial r = w[0];
+    KSum a = {r.plaq_s, r.plaq_c}, bsum = {r.act_s, r.act_c};
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+      kmerge(a, KSum{w[i].plaq_s, w[i].plaq_c});
+      kmerge(bsum, KSum{w[i].act_s, w[i].act_c});
+      r.max_unit = fmax(r.max_unit, w[i].max_unit);
+      r.mism += w[i].mism;
+      r.undef += w[i].undef;
+      r.nonfin += w[i].nonfin;
+    }
+    r.plaq_s = a.s;
+    r.plaq_c = a.c;
+    r.act_s = bsum.s;
+    r.act_c = bsum.c;
+    part[blockIdx.x] = r;
+  }
+}
+
+// One block of 256: fixed-order reduction of the block partials into a record,
+// plus the rejection counter (read, then cleared for the next interval).
+template <typename R>
+__global__ void __launch_bounds__(256) k_finalize(const Partial* __restrict__ part, uint32_t nparts,
+                                                  double inv18v, double inv36v,
+                                                  unsigned long long* rejected, VsmStatsDev* out,
+                                                  long long sweep) {
+  KSum a = {0.0, 0.0}, b = {0.0, 0.0};
+  double mu = 0.0;
+  long long mism = 0, undef = 0, nonfin = 0;
+  for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+    kmerge(a, KSum{part[i].plaq_s, part[i].plaq_c});
+    kmerge(b, KSum{part[i].act_s, part[i].act_c});
+    mu = fmax(mu, part[i].max_unit);
+    mism += part[i].mism;
+    undef += part[i].undef;
+    nonfin += part[i].nonfin;
+  }
+  __shared__ Partial sh[256];
+  sh[threadIdx.x] = Partial{a.s, a.c, b.s, b.c, mu, 0.0, mism, undef, nonfin, 0};
+  __syncthreads();
+  for (int stride = 128; stride > 0; stride >>= 1) {
+    if ((int)threadIdx.x < stride) {
+      Partial& x = sh[threadIdx.x];
+      const Partial& y = sh[threadIdx.x + stride];
+      KSum pa = {x.plaq_s, x.plaq_c}, pb = {x.act_s, x.act_c};
+      kmerge(pa, KSum{y.plaq_s, y.plaq_c});
+      kmerge(pb, KSum{y.act_s, y.act_c});
+      x.plaq_s = pa.s;
+      x.plaq_c = pa.c;
+      x.act_s = pb.s;
+      x.act_c = pb.c;
+      x.max_unit = fmax(x.max_unit, y.max_unit);
+      x.mism += y.mism;
+      x.undef += y.undef;
+      x.nonfin += y.nonfin;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const Partial& r = sh[0];
+    out->plaq = (r.plaq_s + r.plaq_c) * inv18v;
+    out->action = (r.act_s + r.act_c) * inv36v;
+    out->max_unitarity = r.max_unit;
+    out->sweep = (double)sweep;
+    out->flux_mismatch = r.mism;
+    out->undefined_sector = r.undef;
+    out->nonfinite = r.nonfin;
+    if (rejected) {
+      out->rejected = (long long)*rejected;
+      *rejected = 0ull;
+    } else {
+      out->rejected = 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename R>
+void launch_set_links_t(const Geo& g, const void* canon, void* links, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_links<R>, dim3(blocks_for(4ull * g.V, 256)), dim3(256), 0, st, g,
+                     (const double2*)canon, links);
+}
+
+template <typename R>
+void launch_get_links_t(const Geo& g, const void* links, void* canon, hipStream_t st) {
+  hipLaunchKernelGGL(k_get_links<R>, dim3(blocks_for(4ull * g.V, 256)), dim3(256), 0, st, g, links,
+                     (double2*)canon);
+}
+
+template <typename R>
+void launch_load_z3_t(const Geo& g, const int8_t* z3, void* links, hipStream_t st) {
+  hipLaunchKernelGGL(k_load_z3<R>, dim3(blocks_for(4ull * g.V, 256)), dim3(256), 0, st, g, z3, links);
+}
+
+template <typename R>
+void launch_centrifuge_t(const Geo& g, const int8_t* z3, const int8_t* pair, double omega, void* links,
+                         int32_t* m_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_centrifuge<R>, dim3(blocks_for(4ull * g.V, 256)), dim3(256), 0, st, g, z3, pair,
+                     omega, links, m_out);
+}
+
+template <typename R>
+void launch_gauge_t(const Geo& g, void* links, const void* gauge, hipStream_t st) {
+  hipLaunchKernelGGL(k_gauge<R>, dim3(blocks_for(4ull * g.V, 256)), dim3(256), 0, st, g, links,
+                     (const double2*)gauge);
+}
+
+template <typename R, int MU>
+void launch_update_mu(const Geo& g, const void* src, void* dst, const int8_t* z3, const void* gauge,
+                      const UpdParams& p, int colour, int jacobi, unsigned long long* rej,
+                      hipStream_t st) {
+  const uint32_t n = jacobi ? g.V : g.V4;
+  const unsigned nb = blocks_for(n, 256);
+  const double2* gp = (const double2*)gauge;
+  if (p.oi) {
+    if (p.update == 0)
+      hipLaunchKernelGGL((k_update<R, MU, true, 0>), dim3(nb), dim3(256), 0, st, g, src, dst, z3, gp, p,
+                         colour, jacobi, n, rej);
+    else
+      hipLaunchKernelGGL((k_update<R, MU, true, 1>), dim3(nb), dim3(256), 0, st, g, src, dst, z3, gp, p,
+                         colour, jacobi, n, rej);
+  } else {
+    if (p.update == 0)
+      hipLaunchKernelGGL((k_update<R, MU, false, 0>), dim3(nb), dim3(256), 0, st, g, src, dst, z3, gp, p,
+                         colour, jacobi, n, rej);
+    else
+      hipLaunchKernelGGL((k_update<R, MU, false, 1>), dim3(nb), dim3(256), 0, st, g, src, dst, z3, gp, p,
+                         colour, jacobi, n, rej);
+  }
+}
+
+template <typename R>
+void launch_update_t(const Geo& g, const void* src, void* dst, const int8_t* z3, const void* gauge,
+                     const UpdParams& p, int mu, int colour, int jacobi, unsigned long long* rej,
+                     hipStream_t st) {
+  switch (mu) {
+    case 0: launch_update_mu<R, 0>(g, src, dst, z3, gauge, p, colour, jacobi, rej, st); break;
+    case 1: launch_update_mu<R, 1>(g, src, dst, z3, gauge, p, colour, jacobi, rej, st); break;
+    case 2: launch_update_mu<R, 2>(g, src, dst, z3, gauge, p, colour, jacobi, rej, st); break;
+    default: launch_update_mu<R, 3>(g, src, dst, z3, gauge, p, colour, jacobi, rej, st); break;
+  }
+}
+
+template <typename R>
+void launch_measure_t(const Geo& g, const void* links, const int8_t* z3, void* partials, int8_t* flux,
+                      unsigned long long* rej, VsmStatsDev* out, long long sweep, hipStream_t st) {
+  const unsigned nb = blocks_for(g.V, 256);
+  hipLaunchKernelGGL(k_measure<R>, dim3(nb), dim3(256), 0, st, g, links, z3, (Partial*)partials, flux);
+  hipLaunchKernelGGL(k_finalize<R>, dim3(1), dim3(256), 0, st, (const Partial*)partials, nb,
+                     1.0 / (18.0 * (double)g.V), 1.0 / (36.0 * (double)g.V), rej, out, sweep);
+}
+
+}  // namespace vsm

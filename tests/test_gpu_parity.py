@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: integer outputs (centrifuge m, vortex flux, counts) bit-exact; FP64 links
+within 1e-12 of the oracle (max entry, entries are O(1)); FP64 scalars within
+1e-12 relative.  The FP32-bulk form is checked against bounds stated per test.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+import oracle as ora
+from paper_2203_09764_amd import api
+
+pytestmark = pytest.mark.gpu
+
+LINK_TOL = 1e-12
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def _field(dims, precision="fp64"):
+    return api.Field(dims, precision, device=_dev())
+
+
+def _haar(dims, seed):
+    V = fieldgen.volume(dims)
+    return fieldgen.haar_su3(4 * V, seed).reshape(4, V, 3, 3).copy()
+
+
+def _links(f):
+    return api.get_links(f).cpu().numpy()
+
+
+def _stats(t, n):
+    return api.stats_to_numpy(t, n)
+
+
+def _prep(dims, p, seed, omega=0.02, precision="fp64"):
+    n = fieldgen.z3_vortex_charges(dims, p, seed)
+    pairs = fieldgen.centrifuge_pairs(dims, seed + 1)
+    f = _field(dims, precision)
+    f.set_charges(n)
+    api.precondition(f, pairs, omega)
+    return f, n, ora.centrifuge(dims, n, pairs, omega)
+
+
+def test_library_loaded_is_the_hip_build():
+    assert "gfx950" in api.version()
+    assert torch.cuda.is_available()
+
+
+def test_z3_ingest_matches_oracle():
+    dims = (8, 8, 8, 12)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 1)
+    f = _field(dims)
+    api.load_z3(f, n)
+    got = _links(f)
+    want = ora.z3_field(dims, n)
+    assert np.abs(got - want).max() < 3e-16
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (4, 8, 12, 16), (12, 4, 8, 4)])
+def test_centrifuge_matches_oracle(dims):
+    n = fieldgen.z3_vortex_charges(dims, 0.15, 3)
+    pairs = fieldgen.centrifuge_pairs(dims, 4)
+    f = _field(dims)
+    f.set_charges(n)
+    m = api.precondition(f, pairs, 0.02, want_m=True)
+    want, m_ora = ora.centrifuge(dims, n, pairs, 0.02, return_m=True)
+    np.testing.assert_array_equal(m.cpu().numpy(), m_ora)
+    assert np.abs(_links(f) - want).max() < 1e-15
+
+
+def test_set_get_roundtrip():
+    dims = (4, 4, 4, 8)
+    U = _haar(dims, 5)
+    f = _field(dims)
+    api.set_links(f, torch.from_numpy(U))
+    np.testing.assert_array_equal(_links(f), U)
+    g = _field(dims, "fp32_bulk")
+    api.set_links(g, torch.from_numpy(U))
+    np.testing.assert_array_equal(_links(g), U.astype(np.complex64).astype(np.complex128))
+
+
+@pytest.mark.parametrize("kind", ["centrifuged", "haar"])
+def test_measure_matches_oracle(kind):
+    dims = (8, 8, 8, 8)
+    n = fieldgen.z3_vortex_charges(dims, 0.12, 7)
+    if kind == "haar":
+        U = _haar(dims, 8)
+    else:
+        U = ora.centrifuge(dims, n, fieldgen.centrifuge_pairs(dims, 9), 0.02)
+    f = _field(dims)
+    f.set_charges(n)
+    api.set_links(f, torch.from_numpy(U))
+    st, flux = api.measure(f, with_flux=True)
+    s = _stats(st, 1)[0]
+    o, oflux = ora.measure(dims, U, n, with_flux=True)
+    assert abs(s.plaq - o.plaq) <= 1e-13 * abs(o.plaq)
+    assert abs(s.action - o.action) <= 1e-13 * abs(o.action)
+    np.testing.assert_array_equal(flux.cpu().numpy(), oflux)
+    assert s.flux_mismatch == o.flux_mismatch
+    assert s.undefined_sector == o.undefined_sector
+    assert s.nonfinite == 0 and s.max_unitarity < 1e-14
+
+
+@pytest.mark.parametrize("eps", [1.0, -0.25])
+@pytest.mark.parametrize("mu,colour", [(0, 0), (0, 3), (1, 2), (2, 1), (3, 0)])
+def test_single_pass_full_su3(eps, mu, colour):
+    """One annealing subset on a Haar-random field (every SU(3) entry non-zero)."""
+    dims = (8, 4, 8, 12)
+    U = _haar(dims, 100 + mu)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 11)
+    f = _field(dims)
+    f.set_charges(n)
+    api.set_links(f, torch.from_numpy(U))
+    api.anneal_pass(f, mu, colour, 0.3, eps)
+    want = U.copy()
+    ora.anneal_pass(dims, want, n, mu, colour, rho=0.3, eps=eps)
+    assert np.abs(_links(f) - want).max() < 1e-13
+
+
+def test_c0_jacobi_plain_stout():
+    """8^4 vortex field (p = 0.05), centrifuge 0.02, 10 plain stout sweeps rho = 0.1."""
+    c = fieldgen.CONFIGS["c0"]
+    dims = c["dims"]
+    f, n, U = _prep(dims, c["p"], c["field_seed"], c["omega"])
+    n2 = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
+    pairs = fieldgen.centrifuge_pairs(dims, c["pair_seed"])
+    f.set_charges(n2)
+    api.precondition(f, pairs, c["omega"])
+    U = ora.centrifuge(dims, n2, pairs, c["omega"])
+    st = api.smooth(f, c["n_sweeps"], c["rho"], c["eps"], order="jacobi", measure_every=1)
+    so = ora.smooth(dims, U, n2, c["n_sweeps"], order="jacobi", rho=c["rho"], eps=c["eps"])
+    s = _stats(st, c["n_sweeps"])
+    np.testing.assert_allclose(s.plaq, so.plaq, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(s.action, so.action, rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(s.flux_mismatch, so.flux_mismatch)
+    assert np.abs(_links(f) - U).max() < LINK_TOL
+
+
+def test_c1_short_annealed_oi_vp():
+    """16^3 x 32, p = 0.1, the annealed over-improved stout recipe with VP, 3 sweeps."""
+    c = fieldgen.CONFIGS["c1"]
+    dims = c["dims"]
+    n = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
+    pairs = fieldgen.centrifuge_pairs(dims, c["pair_seed"])
+    f = _field(dims)
+    f.set_charges(n)
+    api.precondition(f, pairs, c["omega"])
+    U = ora.centrifuge(dims, n, pairs, c["omega"])
+    st = api.smooth(f, 3, c["rho"], c["eps"], order="annealed", vp=True, measure_every=1)
+    so = ora.smooth(dims, U, n, 3, order="annealed", rho=c["rho"], eps=c["eps"], vp=True)
+    s = _stats(st, 3)
+    np.testing.assert_allclose(s.plaq, so.plaq, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(s.action, so.action, rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(s.flux_mismatch, 0)
+    np.testing.assert_array_equal(s.rejected, so.rejected)
+    assert np.abs(_links(f) - U).max() < LINK_TOL
+
+
+@pytest.mark.parametrize("order", ["jacobi", "annealed"])
+def test_random_gauge_variant_full_su3(order):
+    """The preconditioned field in a Haar-random gauge, smoothed with VP undoing the
+    gauge in its test (Sec. VI); stout with plain (Jacobi) or OI (annealed) staples."""
+    dims = (8, 8, 8, 8)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 21)
+    pairs = fieldgen.centrifuge_pairs(dims, 22)
+    G = fieldgen.haar_su3(fieldgen.volume(dims), 23)
+    f = _field(dims)
+    f.set_charges(n)
+    api.precondition(f, pairs, 0.05)
+    api.gauge_transform(f, torch.from_numpy(G))
+    U = ora.gauge_transform(dims, ora.centrifuge(dims, n, pairs, 0.05), G)
+    assert np.abs(_links(f) - U).max() < 1e-14
+    eps = 1.0 if order == "jacobi" else -0.25
+    st = api.smooth(f, 3, 0.1, eps, order=order, vp=True, gauge=torch.from_numpy(G), measure_every=1)
+    so = ora.smooth(dims, U, n, 3, order=order, rho=0.1, eps=eps, vp=True, gauge=G)
+    s = _stats(st, 3)
+    np.testing.assert_array_equal(s.rejected, so.rejected)
+    np.testing.assert_allclose(s.plaq, so.plaq, rtol=1e-12, atol=0)
+    assert np.abs(_links(f) - U).max() < LINK_TOL
+
+
+@pytest.mark.parametrize("alpha,eps", [(1.0, 1.0), (0.7, -0.25), (0.02, -0.25)])
+def test_maxretr_annealed_random_gauge(alpha, eps):
+    """MaxReTr (Sec. III): cooling (alpha = 1) and AUS (alpha = 0.7, 0.02) on a
+    random-gauge field, annealed, 3 subgroup loops."""
+    dims = (8, 8, 4, 8)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 31)
+    pairs = fieldgen.centrifuge_pairs(dims, 32)
+    G = fieldgen.haar_su3(fieldgen.volume(dims), 33)
+    U = ora.gauge_transform(dims, ora.centrifuge(dims, n, pairs, 0.02), G)
+    f = _field(dims)
+    f.set_charges(n)
+    api.set_links(f, torch.from_numpy(U))
+    st = api.smooth(f, 2, 0.0, eps, order="annealed", update="maxretr", alpha=alpha,
+                    measure_every=1)
+    so = ora.smooth(dims, U, n, 2, order="annealed", update="maxretr", alpha=alpha, eps=eps)
+    np.testing.assert_allclose(_stats(st, 2).plaq, so.plaq, rtol=1e-12, atol=0)
+    assert np.abs(_links(f) - U).max() < 1e-11
+
+
+def test_centre_field_unchanged_bit_identical():
+    """Sec. II.A: a centre field has Q = 0 and is left unchanged by stout."""
+    dims = (8, 8, 8, 8)
+    n = fieldgen.z3_vortex_charges(dims, 0.2, 41)
+    f = _field(dims)
+    api.load_z3(f, n)
+    before = _links(f)
+    api.smooth(f, 3, 0.1, -0.25, order="annealed", vp=True)
+    api.smooth(f, 2, 0.1, 1.0, order="jacobi")
+    np.testing.assert_array_equal(_links(f), before)
+
+
+def test_deterministic_and_resumable():
+    dims = (8, 8, 8, 8)
+    f1, n, _ = _prep(dims, 0.1, 51)
+    f2, _, _ = _prep(dims, 0.1, 51)
+    api.smooth(f1, 4, 0.06, -0.25, order="annealed", vp=True)
+    api.smooth(f2, 1, 0.06, -0.25, order="annealed", vp=True)
+    api.smooth(f2, 3, 0.06, -0.25, order="annealed", vp=True)
+    np.testing.assert_array_equal(_links(f1), _links(f2))
+
+
+def test_fp32_bulk_error_bound():
+    """FP32-bulk form on the annealed OI VP recipe: links within 2e-6 of the FP64
+    oracle after 3 sweeps; flux exact (VP)."""
+    dims = (8, 8, 8, 8)
+    f, n, U = _prep(dims, 0.1, 61, precision="fp32_bulk")
+    st = api.smooth(f, 3, 0.06, -0.25, order="annealed", vp=True, measure_every=1)
+    so = ora.smooth(dims, U, n, 3, order="annealed", rho=0.06, eps=-0.25, vp=True)
+    s = _stats(st, 3)
+    err = np.abs(_links(f) - U).max()
+    assert err < 2e-6, err
+    np.testing.assert_array_equal(s.flux_mismatch, 0)
+    np.testing.assert_allclose(s.action, so.action, rtol=1e-5)
+
+
+def test_api_errors_do_not_launch():
+    dims = (8, 8, 8, 8)
+    f = _field(dims)
+    with pytest.raises(api._lib.VsmError):
+        api.precondition(f, np.zeros((4, f.V), np.int8), 0.3, z3=np.zeros((4, f.V), np.int8))
+    g = _field(dims)
+    with pytest.raises(api._lib.VsmError):
+        api.smooth(g, 1, 0.1, 1.0, order="annealed", vp=True)  # no charges given
+    with pytest.raises(api._lib.VsmError):
+        api.Field((8, 8, 6, 8)).dims and api.smooth(api.Field((8, 8, 6, 8)), 1, 0.1, 1.0,
+                                                     order="annealed")
