@@ -1,0 +1,212 @@
+"""Benchmark of the vortex-field smoothing path on one MI355X.
+
+Workload (default c4): a 48^3 x 96 Z(3) vortex field (p = 0.1), centrifuge
+preconditioning (omega = 0.02), then annealed over-improved stout sweeps
+(rho = 0.06, eps = -0.25, u0 = 1) with vortex preservation and one measurement
+record (plaquette, action, vortex-flux check) after every sweep.  One "step" is
+one such sweep: 16 subset passes over all 4V links plus the measurement.
+
+Prints ONE JSON line.  value = link updates per second (4V per sweep) of the
+whole timed region (inputs resident in HBM, K sweeps, both ends synchronised).
+roofline = the dominant kernel (one annealing subset pass) against HBM
+bandwidth: algorithmic bytes per launch / the average launch duration measured
+with HIP events on the library's stream.  cpu_baseline = the FP64 CPU oracle
+timed on a bounded sample (the first subset passes of the same field, ~10 s).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+WORKLOADS = {
+    "c4": "48^3x96 Z(3) vortex field p=0.1, centrifuge omega=0.02, annealed over-improved stout "
+          "rho=0.06 eps=-0.25 with vortex preservation, measurement every sweep",
+    "c2": "32^3x64 Z(3) vortex field p=0.1, centrifuge omega=0.02, annealed over-improved stout "
+          "rho=0.06 eps=-0.25 with vortex preservation, measurement every sweep",
+    "c1": "16^3x32 Z(3) vortex field p=0.1, centrifuge omega=0.02, annealed over-improved stout "
+          "rho=0.06 eps=-0.25 with vortex preservation, measurement every sweep",
+}
+
+
+def pass_bytes_per_lu(precision: str) -> int:
+    """Algorithmic HBM bytes per link update of one annealing subset pass: the
+    pass reads every link of the lattice once (4V links for V/4 updates = 16 per
+    update), writes the updated link, and reads its original charge (1 byte)."""
+    link = 144 if precision == "fp64" else 72
+    return 16 * link + link + 1
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2203_09764_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, precision: str, launch_lu: int):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, or None
+    when it is missing or was taken on different kernel sources."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def run_gpu_form(args, precision, dims, n, pairs):
+    import torch
+
+    from paper_2203_09764_amd import api
+
+    c = dict(rho=0.06, eps=-0.25)
+    f = api.Field(dims, precision, device="cuda:0", jacobi_workspace=False)
+    f.set_charges(n)
+    api.precondition(f, pairs, 0.02)
+    stream = torch.cuda.current_stream()
+    # warmup
+    if args.warmup > 0:
+        api.smooth(f, args.warmup, c["rho"], c["eps"], order="annealed", vp=True, measure_every=1)
+    torch.cuda.synchronize()
+    stats = api.new_stats(args.steps, f.device)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    api.smooth(f, args.steps, c["rho"], c["eps"], order="annealed", vp=True, measure_every=1,
+               stats=stats)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    st = api.stats_to_numpy(stats, args.steps)
+    V = f.V
+    lu = 4 * V * args.steps
+    # dominant kernel: one subset pass, timed launch by launch with events
+    npass = 16 * args.pass_sweeps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(npass + 1)]
+    k = 0
+    evs[0].record(stream)
+    for _ in range(args.pass_sweeps):
+        for mu in range(4):
+            for colour in (0, 2, 1, 3):
+                api.anneal_pass(f, mu, colour, c["rho"], c["eps"], vp=True)
+                k += 1
+                evs[k].record(stream)
+    torch.cuda.synchronize()
+    durs = [evs[i].elapsed_time(evs[i + 1]) for i in range(npass)]
+    avg_pass_ms = sum(durs) / len(durs)
+    launch_lu = V // 4
+    algo_bytes = launch_lu * pass_bytes_per_lu(precision)
+    achieved = algo_bytes / (avg_pass_ms * 1e-3) / 1e9
+    return dict(
+        precision=precision, ms=ms, wall_s=wall, lu_per_s=lu / (ms * 1e-3),
+        ms_per_step=ms / args.steps, avg_pass_ms=avg_pass_ms, pass_launch_lu=launch_lu,
+        pass_algo_bytes=algo_bytes, achieved_gbs=achieved,
+        action=[float(a) for a in st.action], plaq_last=float(st.plaq[-1]),
+        flux_mismatch=int(st.flux_mismatch.sum()), nonfinite=int(st.nonfinite.sum()),
+        max_unitarity=float(st.max_unitarity.max()), rejected=int(st.rejected.sum()),
+    )
+
+
+def cpu_baseline(dims, n, pairs, threads):
+    """The FP64 oracle on the first subset passes (about 10 s) of the same field."""
+    import oracle
+
+    used = oracle.set_threads(threads) if threads > 0 else oracle.set_threads(0)
+    U = oracle.centrifuge(dims, n, pairs, 0.02)
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    done, dt, k = 0, 0.0, 0
+    order = [(mu, c) for mu in range(4) for c in (0, 2, 1, 3)]
+    while k < len(order) and (dt < 10.0 or k < 1):  # about 10 s of CPU work
+        mu, c = order[k]
+        t = time.perf_counter()
+        oracle.anneal_pass(dims, U, n, mu, c, rho=0.06, eps=-0.25, vp=True)
+        dt += time.perf_counter() - t
+        done += V // 4
+        k += 1
+    return dict(value=done / dt, unit="link-updates/s", cores=int(used), kind="oracle",
+                sample=f"the first {k} annealing subset passes of the first sweep of the same "
+                       f"preconditioned field: {done} link updates in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed sweeps (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="both", choices=["fp64", "fp32_bulk", "both"])
+    ap.add_argument("--pass-sweeps", type=int, default=4, help="sweeps timed pass by pass for the roofline")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import fieldgen
+
+    cfg = fieldgen.CONFIGS[args.workload]
+    if args.steps is None:
+        args.steps = cfg["n_sweeps"]
+    dims = cfg["dims"]
+    n = fieldgen.z3_vortex_charges(dims, cfg["p"], cfg["field_seed"])
+    pairs = fieldgen.centrifuge_pairs(dims, cfg["pair_seed"])
+    forms = ["fp64", "fp32_bulk"] if args.precision == "both" else [args.precision]
+    res = {p: run_gpu_form(args, p, dims, n, pairs) for p in forms}
+    head = res["fp64"] if "fp64" in res else res[forms[0]]
+    hp = head["precision"]
+    traffic = load_traffic(args.workload, hp, head["pass_launch_lu"])
+    roof = {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(head["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": f"k_update annealed OI stout pass ({hp})",
+            "algorithmic_bytes_per_launch": head["pass_algo_bytes"],
+            "avg_launch_ms": round(head["avg_pass_ms"], 4)}
+    out = {
+        "metric": "SU(3) link-updates/s per sweep, % HBM roofline",
+        "value": round(head["lu_per_s"], 1),
+        "unit": "link-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if hp == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "lattice": list(dims),
+                   "sweeps": args.steps, "precision": hp},
+        "roofline": roof,
+    }
+    forms_out = {}
+    for p, r in res.items():
+        forms_out[p] = {"lu_per_s": round(r["lu_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                        "avg_pass_ms": round(r["avg_pass_ms"], 4),
+                        "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                        "flux_mismatch": r["flux_mismatch"], "nonfinite": r["nonfinite"],
+                        "max_unitarity": r["max_unitarity"], "final_action": r["action"][-1]}
+    if "fp64" in res and "fp32_bulk" in res:
+        a64, a32 = res["fp64"]["action"], res["fp32_bulk"]["action"]
+        forms_out["fp32_bulk"]["speedup_vs_fp64"] = round(res["fp32_bulk"]["lu_per_s"] / res["fp64"]["lu_per_s"], 3)
+        forms_out["fp32_bulk"]["max_rel_action_dev_vs_fp64"] = max(abs(x - y) / abs(y) for x, y in zip(a32, a64))
+    out["forms"] = forms_out
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(dims, n, pairs, args.cpu_threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
