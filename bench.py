@@ -155,7 +155,22 @@ def main():
     ap.add_argument("--pass-sweeps", type=int, default=4, help="sweeps timed pass by pass for the roofline")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+
+        nb = args.copy_calibration << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb, "copies": 5}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

@@ -31,25 +31,49 @@ int check_dims_impl(const int32_t dims[4], int32_t order, int32_t precision) {
   if (order != VSM_JACOBI && order != VSM_ANNEALED) return VSM_E_PARAM;
   uint64_t V = 1;
   for (int d = 0; d < 4; ++d) {
-    if (dims[d] < 4) return VSM_E_DIMS;
-    if (order == VSM_ANNEALED && dims[d] % 4) return VSM_E_DIMS;
+    if (dims[d] < 4 || dims[d] % 4) return VSM_E_DIMS;
     V *= (uint64_t)dims[d];
   }
-  if (dims[0] % 4) return VSM_E_DIMS;
   if (9ull * V * entry_bytes(precision) >= (1ull << 31)) return VSM_E_DIMS;
   return VSM_OK;
 }
 
+// Internal axis 0 (blocked by 4, fastest in memory) is the longest user axis,
+// preferring one whose rows of L/4 FP64 entries fill whole 128-byte lines; the
+// other user axes follow in their own order.  Directions are relabelled with
+// the axes, which leaves the annealing subsets unchanged.
 Geo make_geo(const int32_t dims[4]) {
+  int a0 = 0;
+  auto score = [&](int d) { return (long)dims[d] * 2 + (((dims[d] / 4) * 16) % 128 == 0 ? 1 : 0); };
+  for (int d = 1; d < 4; ++d)
+    if (score(d) > score(a0)) a0 = d;
   Geo g;
-  for (int d = 0; d < 4; ++d) g.L[d] = dims[d];
-  g.Xq = dims[0] / 4;
-  g.V = (uint32_t)dims[0] * (uint32_t)dims[1] * (uint32_t)dims[2] * (uint32_t)dims[3];
+  g.perm[a0] = 0;
+  g.uperm[0] = a0;
+  int k = 1;
+  for (int d = 0; d < 4; ++d)
+    if (d != a0) {
+      g.perm[d] = k;
+      g.uperm[k] = d;
+      ++k;
+    }
+  uint32_t cstride[4];
+  uint32_t acc = 1;
+  for (int d = 0; d < 4; ++d) {
+    cstride[d] = acc;
+    acc *= (uint32_t)dims[d];
+  }
+  for (int i = 0; i < 4; ++i) {
+    g.L[i] = dims[g.uperm[i]];
+    g.cst[i] = cstride[g.uperm[i]];
+  }
+  g.Xq = g.L[0] / 4;
+  g.V = acc;
   g.V4 = g.V / 4;
-  g.st[0] = 1;
-  g.st[1] = (uint32_t)g.Xq;
-  g.st[2] = (uint32_t)g.Xq * (uint32_t)dims[1];
-  g.st[3] = (uint32_t)g.Xq * (uint32_t)dims[1] * (uint32_t)dims[2];
+  g.jst[0] = 1;
+  g.jst[1] = (uint32_t)g.Xq;
+  g.jst[2] = (uint32_t)g.Xq * (uint32_t)g.L[1];
+  g.jst[3] = (uint32_t)g.Xq * (uint32_t)g.L[1] * (uint32_t)g.L[2];
   return g;
 }
 
@@ -107,7 +131,7 @@ const char* vsm_version(void) { return "vsm 1.0 (gfx950)"; }
 const char* vsm_strerror(int status) {
   switch (status) {
     case VSM_OK: return "ok";
-    case VSM_E_DIMS: return "lattice extents not allowed (>= 4, Lx % 4 == 0, all % 4 == 0 when annealed, 9*V*entry < 2^31)";
+    case VSM_E_DIMS: return "lattice extents not allowed (each >= 4 and a multiple of 4, 9*V*entry < 2^31)";
     case VSM_E_PARAM: return "parameter outside its domain";
     case VSM_E_NULL: return "required pointer is NULL";
     case VSM_E_WORKSPACE: return "workspace too small";
@@ -210,15 +234,15 @@ int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const 
   for (int sw = 0; sw < n_sweeps; ++sw) {
     if (sched->order == VSM_JACOBI) {
       for (int mu = 0; mu < 4; ++mu)
-        launch_update(precision, g, cur, other, z3_dev, gauge_dev, p, mu, 0, 1, rej, st);
+        launch_update(precision, g, cur, other, z3_dev, gauge_dev, p, g.perm[mu], 0, 1, rej, st);
       void* t = cur;
       cur = other;
       other = t;
     } else {
       for (int mu = 0; mu < 4; ++mu)
         for (int c = 0; c < 4; ++c)
-          launch_update(precision, g, links_dev, links_dev, z3_dev, gauge_dev, p, mu, kColours[c], 0,
-                        rej, st);
+          launch_update(precision, g, links_dev, links_dev, z3_dev, gauge_dev, p, g.perm[mu], kColours[c],
+                        0, rej, st);
     }
     if (measure_every > 0 && (sw + 1) % measure_every == 0) {
       launch_measure(precision, g, cur, z3_dev, ws + w.partials, nullptr, rej, out + rec, sw + 1, st);
@@ -247,7 +271,8 @@ int vsm_pass(const int32_t dims[4], int32_t precision, void* links_dev, const in
   if (workspace_bytes < w.total) return VSM_E_WORKSPACE;
   const UpdParams p = make_params(rho, eps, sched);
   unsigned long long* rej = (unsigned long long*)((char*)workspace_dev + w.counters);
-  launch_update(precision, make_geo(dims), links_dev, links_dev, z3_dev, gauge_dev, p, mu, colour, 0, rej,
+  const Geo g = make_geo(dims);
+  launch_update(precision, g, links_dev, links_dev, z3_dev, gauge_dev, p, g.perm[mu], colour, 0, rej,
                 (hipStream_t)stream);
   return hip_status();
 }

@@ -7,13 +7,17 @@
 //    054501 (2004), the stout reference of Sec. II.A) with FP64 coefficients;
 //  * reunitarisation and the Z(3) sector test of Eq. (centre_element).
 //
-// Internal layout.  Sites are blocked by x mod 4 so that the links of one
-// annealing subset sit in contiguous runs:
-//   idx(x, y, z, t) = (x & 3) * V/4 + (x >> 2) + Xq * (y + Ly * (z + Lz * t)),  Xq = Lx/4.
-// Each direction mu owns 9 arrays of V complex entries (row-major 3x3 entry e):
+// Internal layout.  The lattice axes are relabelled so that internal axis 0 is
+// the longest one; every extent is a multiple of 4.  A site with internal
+// coordinates (c0, c1, c2, c3) has the sublattice s = (c0 + c1 + c2 + c3) mod 4
+// and the position j = (c0 >> 2) + Xq * (c1 + L1 * (c2 + L2 * c3)), Xq = L0 / 4,
+// and lives at idx = s * V/4 + j.  The links of one annealing subset of a
+// direction mu != 0 then fill long contiguous runs of j (the subset is
+// s = (colour - c_mu) mod 4), and so does every neighbour of them.
+// Each direction owns 9 arrays of V complex entries (row-major 3x3 entry e):
 //   entry e of link (mu, idx) lives at element (mu * 9 + e) * V + idx,
-// stored as R2 = {re, im}.  A wave reads 64 consecutive idx values of one entry
-// in one 1 KiB (FP64) or 512 B (FP32) coalesced request.
+// stored as R2 = {re, im}; a wave reads 64 consecutive idx of one entry in one
+// 1 KiB (FP64) or 512 B (FP32) request.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -150,54 +154,70 @@ __device__ __forceinline__ M3<D> mconvert(const M3<S>& x) {
 // ------------------------------------------------------------------ geometry
 
 struct Geo {
-  int L[4];       // extents (x, y, z, t)
-  int Xq;         // Lx / 4
-  uint32_t V;     // sites
-  uint32_t V4;    // V / 4
-  uint32_t st[4]; // idx stride of one step along y, z, t (st[0] unused)
+  int L[4];        // internal extents; axis 0 is blocked by 4 and fastest in memory
+  int Xq;          // L[0] / 4
+  uint32_t V;      // sites
+  uint32_t V4;     // V / 4
+  uint32_t jst[4]; // j stride of internal axes 1..3 (jst[0] unused)
+  uint32_t cst[4]; // canonical-index stride of internal axis d
+  int perm[4];     // internal axis of user axis mu
+  int uperm[4];    // user axis of internal axis d
 };
 
-// Contribution of coordinate value c along direction d to the blocked index.
-__device__ __forceinline__ int coord_term(const Geo& g, int d, int c) {
-  return d == 0 ? (int)((uint32_t)(c & 3) * g.V4) + (c >> 2) : c * (int)g.st[d];
+__device__ __forceinline__ uint32_t site_index(const Geo& g, const int c[4]) {
+  const uint32_t s = (uint32_t)(c[0] + c[1] + c[2] + c[3]) & 3u;
+  const uint32_t j = (uint32_t)(c[0] >> 2) + (uint32_t)c[1] * g.jst[1] + (uint32_t)c[2] * g.jst[2] +
+                     (uint32_t)c[3] * g.jst[3];
+  return s * g.V4 + j;
 }
 
-// Index change for a step of k (|k| <= 2) along direction d from coordinate c.
-__device__ __forceinline__ int delta(const Geo& g, int d, int c, int k) {
-  int cn = c + k;
-  if (cn < 0) cn += g.L[d];
-  if (cn >= g.L[d]) cn -= g.L[d];
-  return coord_term(g, d, cn) - coord_term(g, d, c);
-}
-
-__device__ __forceinline__ uint32_t blocked_index(const Geo& g, const int c[4]) {
-  return (uint32_t)coord_term(g, 0, c[0]) + (uint32_t)c[1] * g.st[1] + (uint32_t)c[2] * g.st[2] +
-         (uint32_t)c[3] * g.st[3];
-}
-
-__device__ __forceinline__ void coords_of_blocked(const Geo& g, uint32_t idx, int c[4]) {
-  uint32_t q = idx / g.V4;
-  uint32_t j = idx - q * g.V4;
-  uint32_t xi = j % (uint32_t)g.Xq;
+__device__ __forceinline__ void coords_of_index(const Geo& g, uint32_t idx, int c[4]) {
+  const uint32_t s = idx / g.V4;
+  const uint32_t j = idx - s * g.V4;
+  const uint32_t xi = j % (uint32_t)g.Xq;
   uint32_t r = j / (uint32_t)g.Xq;
-  c[0] = (int)(4 * xi + q);
   c[1] = (int)(r % (uint32_t)g.L[1]);
   r /= (uint32_t)g.L[1];
   c[2] = (int)(r % (uint32_t)g.L[2]);
   c[3] = (int)(r / (uint32_t)g.L[2]);
+  c[0] = (int)(4 * xi) + (int)((s - (uint32_t)(c[1] + c[2] + c[3])) & 3u);
 }
 
+// Canonical site index s = x + Lx (y + Ly (z + Lz t)) of internal coordinates.
 __device__ __forceinline__ uint32_t canonical_index(const Geo& g, const int c[4]) {
-  return (uint32_t)c[0] + (uint32_t)g.L[0] * ((uint32_t)c[1] + (uint32_t)g.L[1] * ((uint32_t)c[2] + (uint32_t)g.L[2] * (uint32_t)c[3]));
+  return (uint32_t)c[0] * g.cst[0] + (uint32_t)c[1] * g.cst[1] + (uint32_t)c[2] * g.cst[2] +
+         (uint32_t)c[3] * g.cst[3];
 }
 
+__device__ __forceinline__ int pick4(const int v[4], int i) {
+  return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
+}
+
+// Internal coordinates of canonical site s.
 __device__ __forceinline__ void coords_of_canonical(const Geo& g, uint32_t s, int c[4]) {
-  c[0] = (int)(s % (uint32_t)g.L[0]);
-  s /= (uint32_t)g.L[0];
-  c[1] = (int)(s % (uint32_t)g.L[1]);
-  s /= (uint32_t)g.L[1];
-  c[2] = (int)(s % (uint32_t)g.L[2]);
-  c[3] = (int)(s / (uint32_t)g.L[2]);
+  int u[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t Lu = (uint32_t)g.L[g.perm[k]];
+    u[k] = (int)(s % Lu);
+    s /= Lu;
+  }
+#pragma unroll
+  for (int d = 0; d < 4; ++d) c[d] = pick4(u, g.uperm[d]);
+}
+
+__device__ __forceinline__ int wrap_add(int v, int k, int L) {
+  int w = v + k;
+  if (w < 0) w += L;
+  if (w >= L) w -= L;
+  return w;
+}
+
+// Change of j for a step of k (|k| <= 2) along internal axis d from coordinate v.
+// The sublattice of the neighbour is (s + k) mod 4: wraps move by L = 0 mod 4.
+__device__ __forceinline__ int jdelta(const Geo& g, int d, int v, int k) {
+  const int w = wrap_add(v, k, g.L[d]);
+  return d == 0 ? (w >> 2) - (v >> 2) : (w - v) * (int)g.jst[d];
 }
 
 // ------------------------------------------------------------------ link access

@@ -19,6 +19,8 @@ namespace vsm {
 
 // ------------------------------------------------------------------ layout
 
+// Threads run over (user direction mu, canonical site s); the link goes to
+// internal direction perm[mu] at site_index(c).
 template <typename R>
 __global__ void k_set_links(Geo g, const double2* __restrict__ canon, void* links) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -27,12 +29,11 @@ __global__ void k_set_links(Geo g, const double2* __restrict__ canon, void* link
   const uint32_t s = tid - (uint32_t)mu * g.V;
   int c[4];
   coords_of_canonical(g, s, c);
-  const uint32_t idx = blocked_index(g, c);
   const double2* src = canon + ((size_t)mu * g.V + s) * 9;
   M3<R> m;
 #pragma unroll
   for (int e = 0; e < 9; ++e) m.a[e] = cx<R>((R)src[e].x, (R)src[e].y);
-  st_link<R>(links, g, mu, idx, m);
+  st_link<R>(links, g, g.perm[mu], site_index(g, c), m);
 }
 
 template <typename R>
@@ -43,9 +44,7 @@ __global__ void k_get_links(Geo g, const void* links, double2* __restrict__ cano
   const uint32_t s = tid - (uint32_t)mu * g.V;
   int c[4];
   coords_of_canonical(g, s, c);
-  const uint32_t idx = blocked_index(g, c);
-  const DirBuf<R> b = dir_buf<R>(links, g, mu);
-  const M3<R> m = ld_link<R>(b, idx);
+  const M3<R> m = ld_link<R>(dir_buf<R>(links, g, g.perm[mu]), site_index(g, c));
   double2* dst = canon + ((size_t)mu * g.V + s) * 9;
 #pragma unroll
   for (int e = 0; e < 9; ++e) dst[e] = make_double2((double)m.a[e].re, (double)m.a[e].im);
@@ -64,7 +63,7 @@ __global__ void k_load_z3(Geo g, const int8_t* __restrict__ z3, void* links) {
   const Cx<double> z = z3_elem(z3[tid]);
   M3<R> m = mzero<R>();
   m.a[0] = m.a[4] = m.a[8] = cx<R>((R)z.re, (R)z.im);
-  st_link<R>(links, g, mu, blocked_index(g, c), m);
+  st_link<R>(links, g, g.perm[mu], site_index(g, c), m);
 }
 
 // ------------------------------------------------------------------ centrifuge
@@ -73,7 +72,8 @@ __global__ void k_load_z3(Geo g, const int8_t* __restrict__ z3, void* links) {
 //   lambda^j = lambda + omega (sigma - lambda),  lambda^k = lambda - omega (sigma - lambda),
 // i.e. e^{i lambda^j} = z(n) e^{+i d}, e^{i lambda^k} = z(n) e^{-i d} with
 // d = omega (2 pi / 18) (m - 6 n), and the third phase stays lambda.  m is the
-// exact integer sum of the 18 neighbouring charges of the six staples.
+// exact integer sum of the 18 neighbouring charges of the six staples.  The
+// thread works on user direction mu and canonical site s.
 template <typename R>
 __global__ void k_centrifuge(Geo g, const int8_t* __restrict__ z3, const int8_t* __restrict__ pair,
                              double omega, void* links, int32_t* __restrict__ m_out) {
@@ -83,20 +83,20 @@ __global__ void k_centrifuge(Geo g, const int8_t* __restrict__ z3, const int8_t*
   const uint32_t s = tid - (uint32_t)mu * g.V;
   int c[4];
   coords_of_canonical(g, s, c);
-  auto nat = [&](int d, int dmu, int dnu, int nu) -> int {
+  const int dmu = g.perm[mu];
+  // charge of user direction d at the site shifted by (i along mu, k along nu)
+  auto nat = [&](int d, int i, int k, int dnu) -> int {
     int e[4] = {c[0], c[1], c[2], c[3]};
-    e[mu] += dmu;
-    e[nu] += dnu;
-    if (e[mu] >= g.L[mu]) e[mu] -= g.L[mu];
-    if (e[nu] < 0) e[nu] += g.L[nu];
-    if (e[nu] >= g.L[nu]) e[nu] -= g.L[nu];
+    e[dmu] = wrap_add(e[dmu], i, g.L[dmu]);
+    e[dnu] = wrap_add(e[dnu], k, g.L[dnu]);
     return (int)z3[(size_t)d * g.V + canonical_index(g, e)];
   };
   int m = 0;
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == mu) continue;
-    m += nat(nu, 0, 0, nu) + nat(mu, 0, 1, nu) - nat(nu, 1, 0, nu);    // upper staple
-    m += -nat(nu, 0, -1, nu) + nat(mu, 0, -1, nu) + nat(nu, 1, -1, nu);  // lower staple
+    const int dnu = g.perm[nu];
+    m += nat(nu, 0, 0, dnu) + nat(mu, 0, 1, dnu) - nat(nu, 1, 0, dnu);     // upper staple
+    m += -nat(nu, 0, -1, dnu) + nat(mu, 0, -1, dnu) + nat(nu, 1, -1, dnu);  // lower staple
   }
   const int n = z3[tid];
   const double d = omega * (2.0 * 3.14159265358979323846 / 18.0) * (double)(m - 6 * n);
@@ -113,23 +113,24 @@ __global__ void k_centrifuge(Geo g, const int8_t* __restrict__ z3, const int8_t*
     const Cx<double> v = (i == j) ? zp : ((i == k) ? zm : z);
     u.a[4 * i] = cx<R>((R)v.re, (R)v.im);
   }
-  st_link<R>(links, g, mu, blocked_index(g, c), u);
+  st_link<R>(links, g, dmu, site_index(g, c), u);
   if (m_out) m_out[tid] = m;
 }
 
 // ------------------------------------------------------------------ gauge transform
 
+// U_mu(x) -> G(x) U_mu(x) G^dagger(x + mu); threads over (internal direction, idx).
 template <typename R>
 __global__ void k_gauge(Geo g, void* links, const double2* __restrict__ gauge) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= 4u * g.V) return;
-  const int mu = (int)(tid / g.V);
-  const uint32_t s = tid - (uint32_t)mu * g.V;
+  const int d = (int)(tid / g.V);
+  const uint32_t idx = tid - (uint32_t)d * g.V;
   int c[4];
-  coords_of_canonical(g, s, c);
-  const uint32_t idx = blocked_index(g, c);
+  coords_of_index(g, idx, c);
+  const uint32_t s = canonical_index(g, c);
   int cp[4] = {c[0], c[1], c[2], c[3]};
-  cp[mu] = (cp[mu] + 1) % g.L[mu];
+  cp[d] = wrap_add(cp[d], 1, g.L[d]);
   const uint32_t sp = canonical_index(g, cp);
   M3<double> G, Gp;
 #pragma unroll
@@ -137,10 +138,9 @@ __global__ void k_gauge(Geo g, void* links, const double2* __restrict__ gauge) {
     G.a[e] = cx<double>(gauge[(size_t)s * 9 + e].x, gauge[(size_t)s * 9 + e].y);
     Gp.a[e] = cx<double>(gauge[(size_t)sp * 9 + e].x, gauge[(size_t)sp * 9 + e].y);
   }
-  const DirBuf<R> b = dir_buf<R>(links, g, mu);
-  const M3<double> u = mconvert<double>(ld_link<R>(b, idx));
+  const M3<double> u = mconvert<double>(ld_link<R>(dir_buf<R>(links, g, d), idx));
   const M3<double> r = mul_nd(mul_nn(G, u), Gp);
-  st_link<R>(links, g, mu, idx, mconvert<R>(r));
+  st_link<R>(links, g, d, idx, mconvert<R>(r));
 }
 
 // ------------------------------------------------------------------ staples
@@ -185,11 +185,18 @@ __device__ __forceinline__ M3<R> chain_start(const DirBuf<R>& b0, uint32_t i0, c
   return r;
 }
 
-// Neighbour offsets of site x (blocked index deltas) along mu and one nu.
+// Neighbours of the thread's site x: x + a mu + b nu has sublattice
+// (S + a + b) mod 4 and position j + dm[a + 1] + dn[b + 2].
 struct Nb {
-  int mm, mp, mp2;            // -mu, +mu, +2mu
-  int nm2, nm, np, np2;       // -2nu, -nu, +nu, +2nu
+  uint32_t j;
+  int S;
+  int dm[4];  // a = -1, 0, 1, 2
+  int dn[5];  // b = -2 .. 2
 };
+
+__device__ __forceinline__ uint32_t nbi(const Geo& g, const Nb& o, int a, int b) {
+  return (uint32_t)((o.S + a + b) & 3) * g.V4 + (uint32_t)((int)o.j + o.dm[a + 1] + o.dn[b + 2]);
+}
 
 // Sigma contribution of one nu and one orientation.  Paths from x to x + mu
 // (a step -d multiplies the adjoint of the link it walks back along):
@@ -201,46 +208,47 @@ struct Nb {
 // Weights: (5 - 2 eps)/3 for the plaquette staple, (eps - 1)/(12 u0^2) for rectangles.
 template <typename R, bool OI, bool UP>
 __device__ __forceinline__ void staple_dir(M3<R>& S, const DirBuf<R>& bm, const DirBuf<R>& bn,
-                                           uint32_t x, const Nb& o, R cp, R cr) {
+                                           const Geo& g, const Nb& o, R cp, R cr) {
+  auto I = [&](int a, int b) { return nbi(g, o, a, b); };
   if (UP) {
-    M3<R> w = chain_start<R, false, false>(bn, x, bm, x + o.np);
-    chain_step<R, true>(w, bn, x + o.mp);
+    M3<R> w = chain_start<R, false, false>(bn, I(0, 0), bm, I(0, 1));
+    chain_step<R, true>(w, bn, I(1, 0));
     maxpy(S, cp, w);
     if (!OI) return;
-    w = chain_start<R, false, false>(bn, x, bn, x + o.np);
-    chain_step<R, false>(w, bm, x + o.np2);
-    chain_step<R, true>(w, bn, x + o.mp + o.np);
-    chain_step<R, true>(w, bn, x + o.mp);
+    w = chain_start<R, false, false>(bn, I(0, 0), bn, I(0, 1));
+    chain_step<R, false>(w, bm, I(0, 2));
+    chain_step<R, true>(w, bn, I(1, 1));
+    chain_step<R, true>(w, bn, I(1, 0));
     maxpy(S, cr, w);
-    w = chain_start<R, false, false>(bn, x, bm, x + o.np);
-    chain_step<R, false>(w, bm, x + o.mp + o.np);
-    chain_step<R, true>(w, bn, x + o.mp2);
-    chain_step<R, true>(w, bm, x + o.mp);
+    w = chain_start<R, false, false>(bn, I(0, 0), bm, I(0, 1));
+    chain_step<R, false>(w, bm, I(1, 1));
+    chain_step<R, true>(w, bn, I(2, 0));
+    chain_step<R, true>(w, bm, I(1, 0));
     maxpy(S, cr, w);
-    w = chain_start<R, true, false>(bm, x + o.mm, bn, x + o.mm);
-    chain_step<R, false>(w, bm, x + o.mm + o.np);
-    chain_step<R, false>(w, bm, x + o.np);
-    chain_step<R, true>(w, bn, x + o.mp);
+    w = chain_start<R, true, false>(bm, I(-1, 0), bn, I(-1, 0));
+    chain_step<R, false>(w, bm, I(-1, 1));
+    chain_step<R, false>(w, bm, I(0, 1));
+    chain_step<R, true>(w, bn, I(1, 0));
     maxpy(S, cr, w);
   } else {
-    M3<R> w = chain_start<R, true, false>(bn, x + o.nm, bm, x + o.nm);
-    chain_step<R, false>(w, bn, x + o.nm + o.mp);
+    M3<R> w = chain_start<R, true, false>(bn, I(0, -1), bm, I(0, -1));
+    chain_step<R, false>(w, bn, I(1, -1));
     maxpy(S, cp, w);
     if (!OI) return;
-    w = chain_start<R, true, true>(bn, x + o.nm, bn, x + o.nm2);
-    chain_step<R, false>(w, bm, x + o.nm2);
-    chain_step<R, false>(w, bn, x + o.nm2 + o.mp);
-    chain_step<R, false>(w, bn, x + o.nm + o.mp);
+    w = chain_start<R, true, true>(bn, I(0, -1), bn, I(0, -2));
+    chain_step<R, false>(w, bm, I(0, -2));
+    chain_step<R, false>(w, bn, I(1, -2));
+    chain_step<R, false>(w, bn, I(1, -1));
     maxpy(S, cr, w);
-    w = chain_start<R, true, false>(bn, x + o.nm, bm, x + o.nm);
-    chain_step<R, false>(w, bm, x + o.nm + o.mp);
-    chain_step<R, false>(w, bn, x + o.nm + o.mp2);
-    chain_step<R, true>(w, bm, x + o.mp);
+    w = chain_start<R, true, false>(bn, I(0, -1), bm, I(0, -1));
+    chain_step<R, false>(w, bm, I(1, -1));
+    chain_step<R, false>(w, bn, I(2, -1));
+    chain_step<R, true>(w, bm, I(1, 0));
     maxpy(S, cr, w);
-    w = chain_start<R, true, true>(bm, x + o.mm, bn, x + o.mm + o.nm);
-    chain_step<R, false>(w, bm, x + o.mm + o.nm);
-    chain_step<R, false>(w, bm, x + o.nm);
-    chain_step<R, false>(w, bn, x + o.nm + o.mp);
+    w = chain_start<R, true, true>(bm, I(-1, 0), bn, I(-1, -1));
+    chain_step<R, false>(w, bm, I(-1, -1));
+    chain_step<R, false>(w, bm, I(0, -1));
+    chain_step<R, false>(w, bn, I(1, -1));
     maxpy(S, cr, w);
   }
 }
@@ -377,11 +385,12 @@ __device__ __noinline__ Cx<double> gauge_undone_trace(const double2* __restrict_
 }
 
 // The thread's link of an annealing subset (Sec. III.A masking).  Subset c of
-// direction mu holds the sites with (2 x_mu + sum_{nu != mu} x_nu) mod 4 = c.
-//   mu != 0: in every row (y, z, t) the subset has one residue q = x mod 4, so
-//            thread t maps to j = t (all x >> 2 of all rows) in sublattice q(row);
-//   mu == 0: only rows with y + z + t of the parity of c take part, with the two
-//            residues q = h, h + 2, h = ((c - y - z - t) mod 4) / 2.
+// direction mu holds the sites with (2 x_mu + sum_{nu != mu} x_nu) mod 4 = c,
+// i.e. with sublattice (x0 + x1 + x2 + x3) mod 4 = (c - x_mu) mod 4 (internal axes).
+//   mu != 0: every position j has exactly one such site, in sublattice
+//            (c - x_mu) mod 4, so thread t takes j = t;
+//   mu == 0: only rows with x1 + x2 + x3 of the parity of c take part, each with
+//            the two residues x0 mod 4 = h, h + 2, h = ((c - x1 - x2 - x3) mod 4) / 2.
 template <int MU>
 __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t, int c[4]) {
   if (MU != 0) {
@@ -391,12 +400,8 @@ __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t
     r /= (uint32_t)g.L[1];
     c[2] = (int)(r % (uint32_t)g.L[2]);
     c[3] = (int)(r / (uint32_t)g.L[2]);
-    int rest = 2 * c[MU];
-#pragma unroll
-    for (int d = 1; d < 4; ++d)
-      if (d != MU) rest += c[d];
-    const int q = (colour - rest) & 3;
-    c[0] = (int)(4 * xi) + q;
+    const int s = (colour - c[MU]) & 3;
+    c[0] = (int)(4 * xi) + ((s - c[1] - c[2] - c[3]) & 3);
   } else {
     const uint32_t two = 2u * (uint32_t)g.Xq;
     const uint32_t k = t / two;
@@ -430,36 +435,43 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* ds
   // XCDs; give each XCD one contiguous range of the lattice for L2 reuse.
   uint32_t b = blockIdx.x;
   const uint32_t nb = gridDim.x;
-  if ((nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
+#ifndef VSM_XCD_REMAP
+#define VSM_XCD_REMAP 1
+#endif
+  if (VSM_XCD_REMAP && (nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
   const uint32_t t = b * blockDim.x + threadIdx.x;
   const bool active = t < nthreads;
   int c[4] = {0, 0, 0, 0};
   if (active) {
     if (jacobi)
-      coords_of_blocked(g, t, c);
+      coords_of_index(g, t, c);
     else
       subset_site<MU>(g, colour, t, c);
   }
   bool rej = false;
   if (active) {
-    const uint32_t x = blocked_index(g, c);
+    const uint32_t x = site_index(g, c);
     const R cp = (R)p.cp, cr = (R)p.cr;
     const DirBuf<R> bm = dir_buf<R>(src, g, MU);
+    Nb o;
+    o.S = (c[0] + c[1] + c[2] + c[3]) & 3;
+    o.j = x - (uint32_t)o.S * g.V4;
+    o.dm[0] = jdelta(g, MU, c[MU], -1);
+    o.dm[1] = 0;
+    o.dm[2] = jdelta(g, MU, c[MU], 1);
+    o.dm[3] = jdelta(g, MU, c[MU], 2);
     M3<R> S = mzero<R>();
 #pragma unroll 1
     for (int nu = 0; nu < 4; ++nu) {
       if (nu == MU) continue;
-      Nb o;
-      o.mm = delta(g, MU, c[MU], -1);
-      o.mp = delta(g, MU, c[MU], 1);
-      o.mp2 = delta(g, MU, c[MU], 2);
-      o.nm2 = delta(g, nu, c[nu], -2);
-      o.nm = delta(g, nu, c[nu], -1);
-      o.np = delta(g, nu, c[nu], 1);
-      o.np2 = delta(g, nu, c[nu], 2);
+      o.dn[0] = jdelta(g, nu, c[nu], -2);
+      o.dn[1] = jdelta(g, nu, c[nu], -1);
+      o.dn[2] = 0;
+      o.dn[3] = jdelta(g, nu, c[nu], 1);
+      o.dn[4] = jdelta(g, nu, c[nu], 2);
       const DirBuf<R> bn = dir_buf<R>(src, g, nu);
-      staple_dir<R, OI, true>(S, bm, bn, x, o, cp, cr);
-      staple_dir<R, OI, false>(S, bm, bn, x, o, cp, cr);
+      staple_dir<R, OI, true>(S, bm, bn, g, o, cp, cr);
+      staple_dir<R, OI, false>(S, bm, bn, g, o, cp, cr);
     }
     const M3<R> U = ld_link(bm, x);
     M3<double> cand;
@@ -480,7 +492,7 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* ds
       } else {
         tr = mtrace(mconvert<double>(cr_));
       }
-      const int n0 = z3[(size_t)MU * g.V + canonical_index(g, c)];
+      const int n0 = z3[(size_t)g.uperm[MU] * g.V + canonical_index(g, c)];
       accept = (z3_sector(tr.re, tr.im) == n0);
     }
     rej = moved && !accept;
@@ -534,24 +546,25 @@ __device__ __forceinline__ int link_sector(const M3<double>& u) {
 // Re Tr P and Re Tr[1 - P] (Sec. V.A); the sectors of the four links at x;
 // the vortex flux of every plaquette from the link sectors compared with the
 // flux of the original charges; unitarity and finiteness of the own links.
+// Threads run over the internal site index; planes and charges use user axes.
 // Block partials go to fixed slots; k_finalize sums them in a fixed order, so
 // the result does not depend on the scheduling.
 template <typename R>
 __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const int8_t* __restrict__ z3,
                                                  Partial* __restrict__ part, int8_t* __restrict__ flux) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   KSum kp = {0.0, 0.0}, ka = {0.0, 0.0};
   double maxu = 0.0;
   long long mism = 0, undef = 0, nonfin = 0;
-  if (s < g.V) {
+  if (x < g.V) {
     int c[4];
-    coords_of_canonical(g, s, c);
-    const uint32_t x = blocked_index(g, c);
-    // sectors and original charges of the four links at x, one byte each
+    coords_of_index(g, x, c);
+    const uint32_t s = canonical_index(g, c);
+    // sectors and original charges of the four links at x (user directions), one byte each
     uint32_t secb = 0, n0b = 0;
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
-      const M3<double> U = mconvert<double>(ld_link(dir_buf<R>(links, g, mu), x));
+      const M3<double> U = mconvert<double>(ld_link(dir_buf<R>(links, g, g.perm[mu]), x));
       const int sc = link_sector(U);
       secb |= (uint32_t)(sc & 0xff) << (8 * mu);
       n0b |= (uint32_t)(z3[(size_t)mu * g.V + s] & 0xff) << (8 * mu);
@@ -571,21 +584,22 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
     auto byte_at = [](uint32_t w, int i) { return (int)(int8_t)((w >> (8 * i)) & 0xffu); };
 #pragma unroll 1
     for (int plane = 0; plane < 6; ++plane) {
-      // planes 01, 02, 03, 12, 13, 23
+      // user planes 01, 02, 03, 12, 13, 23
       const int mu = plane < 3 ? 0 : (plane < 5 ? 1 : 2);
       const int nu = plane < 3 ? plane + 1 : (plane < 5 ? plane - 1 : 3);
+      const int dm = g.perm[mu], dn = g.perm[nu];
       int cm[4] = {c[0], c[1], c[2], c[3]};
-      cm[mu] = (cm[mu] + 1 == g.L[mu]) ? 0 : cm[mu] + 1;
+      cm[dm] = wrap_add(cm[dm], 1, g.L[dm]);
       int cn[4] = {c[0], c[1], c[2], c[3]};
-      cn[nu] = (cn[nu] + 1 == g.L[nu]) ? 0 : cn[nu] + 1;
-      const DirBuf<R> bmu = dir_buf<R>(links, g, mu), bnu = dir_buf<R>(links, g, nu);
+      cn[dn] = wrap_add(cn[dn], 1, g.L[dn]);
+      const DirBuf<R> bmu = dir_buf<R>(links, g, dm), bnu = dir_buf<R>(links, g, dn);
       const M3<double> A = mconvert<double>(ld_link(bmu, x));
       load_fence();
-      const M3<double> B = mconvert<double>(ld_link(bnu, blocked_index(g, cm)));
+      const M3<double> B = mconvert<double>(ld_link(bnu, site_index(g, cm)));
       load_fence();
       const int sb = link_sector(B);
       M3<double> P = mul_nn(A, B);
-      const M3<double> Cm = mconvert<double>(ld_link(bmu, blocked_index(g, cn)));
+      const M3<double> Cm = mconvert<double>(ld_link(bmu, site_index(g, cn)));
       load_fence();
       const int sc = link_sector(Cm);
       P = mul_nd(P, Cm);
