@@ -12,8 +12,8 @@
  * Conventions for every call
  *   dims[4]   lattice extents (Lx, Ly, Lz, Lt), host array.  Every extent must be
  *             >= 4 and a multiple of 4 (the annealing subsets need it).
- *             9 * V * sizeof(entry) must stay below 2^31 bytes (V < 14.9M
- *             sites in FP64, < 29.8M in FP32).
+ *             6 * V * sizeof(entry) must stay below 2^31 bytes (V < 22.3M
+ *             sites in FP64, < 44.7M in FP32).
  *   site      s = x + Lx*(y + Ly*(z + Lz*t)); direction mu = 0..3 = (x, y, z, t).
  *   precision VSM_FP64 (all arithmetic and storage FP64) or VSM_FP32_BULK
  *             (links stored and staples / products computed in FP32; the
@@ -24,6 +24,8 @@
  *             frees or keeps caller buffers.
  *   links     device buffer of vsm_links_bytes(dims, precision) bytes in the
  *             library's internal layout; only the calls below read or write it.
+ *             Links must be SU(3): the library stores rows 0 and 1 and
+ *             rebuilds row 2 as conj(row0 x row1).
  *   stream    hipStream_t passed as void* (NULL = default stream).  Every call
  *             is asynchronous on that stream; none synchronises the host.
  *   status    0 (VSM_OK) on success, a negative VSM_E_* code otherwise.  On an

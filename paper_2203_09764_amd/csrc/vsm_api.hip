@@ -34,7 +34,7 @@ int check_dims_impl(const int32_t dims[4], int32_t order, int32_t precision) {
     if (dims[d] < 4 || dims[d] % 4) return VSM_E_DIMS;
     V *= (uint64_t)dims[d];
   }
-  if (9ull * V * entry_bytes(precision) >= (1ull << 31)) return VSM_E_DIMS;
+  if (6ull * V * entry_bytes(precision) >= (1ull << 31)) return VSM_E_DIMS;
   return VSM_OK;
 }
 
@@ -92,7 +92,7 @@ WsLayout ws_layout(const int32_t dims[4], int32_t precision, int32_t order) {
   w.partials = 256;
   w.field = align256(w.partials + (size_t)measure_blocks(g) * partial_bytes());
   w.total = w.field;
-  if (order == VSM_JACOBI) w.total += align256(36ull * g.V * entry_bytes(precision));
+  if (order == VSM_JACOBI) w.total += align256(24ull * g.V * entry_bytes(precision));
   return w;
 }
 
@@ -131,7 +131,7 @@ const char* vsm_version(void) { return "vsm 1.0 (gfx950)"; }
 const char* vsm_strerror(int status) {
   switch (status) {
     case VSM_OK: return "ok";
-    case VSM_E_DIMS: return "lattice extents not allowed (each >= 4 and a multiple of 4, 9*V*entry < 2^31)";
+    case VSM_E_DIMS: return "lattice extents not allowed (each >= 4 and a multiple of 4, 6*V*entry < 2^31)";
     case VSM_E_PARAM: return "parameter outside its domain";
     case VSM_E_NULL: return "required pointer is NULL";
     case VSM_E_WORKSPACE: return "workspace too small";
@@ -151,7 +151,7 @@ int vsm_check_dims(const int32_t dims[4], int32_t order, int32_t precision) {
 size_t vsm_links_bytes(const int32_t dims[4], int32_t precision) {
   if (check_dims_impl(dims, VSM_JACOBI, precision) != VSM_OK) return 0;
   const Geo g = make_geo(dims);
-  return 36ull * g.V * entry_bytes(precision);
+  return 24ull * g.V * entry_bytes(precision);
 }
 
 size_t vsm_workspace_bytes(const int32_t dims[4], int32_t precision, int32_t order) {
@@ -250,7 +250,7 @@ int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const 
     }
   }
   if (cur != links_dev) {
-    if (hipMemcpyAsync(links_dev, cur, 36ull * g.V * entry_bytes(precision), hipMemcpyDeviceToDevice,
+    if (hipMemcpyAsync(links_dev, cur, 24ull * g.V * entry_bytes(precision), hipMemcpyDeviceToDevice,
                        st) != hipSuccess)
       return hip_status() ? VSM_E_HIP : VSM_E_HIP;
   }

@@ -14,10 +14,12 @@
 // and lives at idx = s * V/4 + j.  The links of one annealing subset of a
 // direction mu != 0 then fill long contiguous runs of j (the subset is
 // s = (colour - c_mu) mod 4), and so does every neighbour of them.
-// Each direction owns 9 arrays of V complex entries (row-major 3x3 entry e):
-//   entry e of link (mu, idx) lives at element (mu * 9 + e) * V + idx,
+// Links are SU(3), so only rows 0 and 1 are stored; row 2 is rebuilt on load as
+// conj(row0 x row1).  Each direction owns 6 arrays of V complex entries
+// (entry e = 3 * row + column, rows 0 and 1):
+//   entry e of link (mu, idx) lives at element (mu * 6 + e) * V + idx,
 // stored as R2 = {re, im}; a wave reads 64 consecutive idx of one entry in one
-// 1 KiB (FP64) or 512 B (FP32) request.
+// 1 KiB (FP64) or 512 B (FP32) request.  A link costs 96 B (FP64) or 48 B (FP32).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,6 +28,7 @@
 namespace vsm {
 
 constexpr int kUndef = -128;
+constexpr uint32_t kStoredEntries = 6;  // rows 0 and 1 of each link
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9-family raw buffer descriptor
 
 // ------------------------------------------------------------------ complex
@@ -128,6 +131,71 @@ __device__ __forceinline__ M3<R> mul_dn(const M3<R>& x, const M3<R>& y) {
   return r;
 }
 
+// Rows 0 and 1 of x * y, x * y^dagger, x^dagger * y (row 2 of the result is
+// left unset).  For SU(3) operands the product is SU(3), so row 2 can be rebuilt
+// afterwards with rebuild_row2 at a third of the cost of computing it.
+template <typename R>
+__device__ __forceinline__ M3<R> mul2_nn(const M3<R>& x, const M3<R>& y) {
+  M3<R> r;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Cx<R> acc = cx<R>(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma(acc, x.a[3 * i + k], y.a[3 * k + j]);
+      r.a[3 * i + j] = acc;
+    }
+  return r;
+}
+
+template <typename R>
+__device__ __forceinline__ M3<R> mul2_nd(const M3<R>& x, const M3<R>& y) {
+  M3<R> r;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Cx<R> acc = cx<R>(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma_c2(acc, x.a[3 * i + k], y.a[3 * j + k]);
+      r.a[3 * i + j] = acc;
+    }
+  return r;
+}
+
+template <typename R>
+__device__ __forceinline__ M3<R> mul2_dn(const M3<R>& x, const M3<R>& y) {
+  M3<R> r;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Cx<R> acc = cx<R>(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma_c1(acc, x.a[3 * k + i], y.a[3 * k + j]);
+      r.a[3 * i + j] = acc;
+    }
+  return r;
+}
+
+// Rows 0 and 1 of x^dagger y^dagger = (y x)^dagger.
+template <typename R>
+__device__ __forceinline__ M3<R> mul2_dd(const M3<R>& x, const M3<R>& y) {
+  M3<R> r;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      // (x^dag y^dag)_ij = conj((y x)_ji) = conj(sum_k y_jk x_ki)
+      Cx<R> acc = cx<R>(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma(acc, y.a[3 * j + k], x.a[3 * k + i]);
+      r.a[3 * i + j] = cx<R>(acc.re, -acc.im);
+    }
+  return r;
+}
+
 // acc += c * x (real c)
 template <typename R>
 __device__ __forceinline__ void maxpy(M3<R>& acc, R c, const M3<R>& x) {
@@ -136,6 +204,16 @@ __device__ __forceinline__ void maxpy(M3<R>& acc, R c, const M3<R>& x) {
     acc.a[e].re = fma(c, x.a[e].re, acc.a[e].re);
     acc.a[e].im = fma(c, x.a[e].im, acc.a[e].im);
   }
+}
+
+template <typename R>
+__device__ __forceinline__ M3<R> madj(const M3<R>& x) {
+  M3<R> r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.a[3 * i + j] = cx<R>(x.a[3 * j + i].re, -x.a[3 * j + i].im);
+  return r;
 }
 
 template <typename R>
@@ -244,9 +322,10 @@ struct DirBuf {
 template <typename R>
 __device__ __forceinline__ DirBuf<R> dir_buf(const void* links, const Geo& g, int mu) {
   const uint32_t es = g.V * (uint32_t)sizeof(typename R2<R>::type);
-  const char* base = (const char*)links + (size_t)mu * 9 * (size_t)es;
+  const char* base = (const char*)links + (size_t)mu * kStoredEntries * (size_t)es;
   DirBuf<R> b;
-  b.rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(9u * es), (int)kRsrcWord3);
+  b.rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(kStoredEntries * es),
+                                           (int)kRsrcWord3);
   b.estride = es;
   return b;
 }
@@ -267,21 +346,44 @@ __device__ __forceinline__ void ld_entry(const DirBuf<float>& b, uint32_t voff, 
   out.im = d.y;
 }
 
+// Row 2 of an SU(3) matrix from rows 0 and 1: r2 = conj(r0 x r1).
+template <typename R>
+__device__ __forceinline__ void rebuild_row2(M3<R>& m) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+    const Cx<R>& a1 = m.a[k1];
+    const Cx<R>& a2 = m.a[k2];
+    const Cx<R>& b1 = m.a[3 + k1];
+    const Cx<R>& b2 = m.a[3 + k2];
+    R re = a1.re * b2.re;
+    re = fma(-a1.im, b2.im, re);
+    re = fma(-a2.re, b1.re, re);
+    re = fma(a2.im, b1.im, re);
+    R im = a1.re * b2.im;
+    im = fma(a1.im, b2.re, im);
+    im = fma(-a2.re, b1.im, im);
+    im = fma(-a2.im, b1.re, im);
+    m.a[6 + k] = cx<R>(re, -im);
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ M3<R> ld_link(const DirBuf<R>& b, uint32_t idx) {
   M3<R> m;
   const uint32_t voff = idx * (uint32_t)sizeof(typename R2<R>::type);
 #pragma unroll
-  for (int e = 0; e < 9; ++e) ld_entry(b, voff, e, m.a[e]);
+  for (int e = 0; e < 6; ++e) ld_entry(b, voff, e, m.a[e]);
+  rebuild_row2(m);
   return m;
 }
 
 template <typename R>
 __device__ __forceinline__ void st_link(void* links, const Geo& g, int mu, uint32_t idx, const M3<R>& m) {
   using T2 = typename R2<R>::type;
-  T2* p = (T2*)links + (size_t)mu * 9 * g.V + idx;
+  T2* p = (T2*)links + (size_t)mu * kStoredEntries * g.V + idx;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
+  for (int e = 0; e < 6; ++e) {
     T2 v;
     v.x = m.a[e].re;
     v.y = m.a[e].im;

@@ -155,11 +155,14 @@ __global__ void k_gauge(Geo g, void* links, const double2* __restrict__ gauge) {
 // still overlap the current product.
 __device__ __forceinline__ void load_fence() { asm volatile("" ::: "memory"); }
 
+// Chain products keep only rows 0 and 1 of the running product (it is a
+// product of SU(3) links, so row 2 follows from them); chain_end rebuilds row 2
+// before the path is added to Sigma.
 template <typename R, bool D>
 __device__ __forceinline__ void chain_step(M3<R>& run, const DirBuf<R>& b, uint32_t i) {
   const M3<R> m = ld_link(b, i);
   load_fence();
-  run = D ? mul_nd(run, m) : mul_nn(run, m);
+  run = D ? mul2_nd(run, m) : mul2_nn(run, m);
 }
 
 template <typename R, bool D0, bool D1>
@@ -169,20 +172,16 @@ __device__ __forceinline__ M3<R> chain_start(const DirBuf<R>& b0, uint32_t i0, c
   load_fence();
   const M3<R> y = ld_link(b1, i1);
   load_fence();
-  M3<R> r;
-  if (!D0 && !D1) r = mul_nn(x, y);
-  if (!D0 && D1) r = mul_nd(x, y);
-  if (D0 && !D1) r = mul_dn(x, y);
-  if (D0 && D1) r = mul_nn(y, x);  // x^dag y^dag = (y x)^dag, adjointed below
-  if (D0 && D1) {
-    M3<R> t;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) t.a[3 * i + j] = cx<R>(r.a[3 * j + i].re, -r.a[3 * j + i].im);
-    r = t;
-  }
-  return r;
+  if (!D0 && !D1) return mul2_nn(x, y);
+  if (!D0 && D1) return mul2_nd(x, y);
+  if (D0 && !D1) return mul2_dn(x, y);
+  return mul2_dd(x, y);
+}
+
+template <typename R>
+__device__ __forceinline__ void chain_add(M3<R>& S, R c, M3<R> w) {
+  rebuild_row2(w);
+  maxpy(S, c, w);
 }
 
 // Neighbours of the thread's site x: x + a mu + b nu has sublattice
@@ -213,44 +212,98 @@ __device__ __forceinline__ void staple_dir(M3<R>& S, const DirBuf<R>& bm, const 
   if (UP) {
     M3<R> w = chain_start<R, false, false>(bn, I(0, 0), bm, I(0, 1));
     chain_step<R, true>(w, bn, I(1, 0));
-    maxpy(S, cp, w);
+    chain_add(S, cp, w);
     if (!OI) return;
     w = chain_start<R, false, false>(bn, I(0, 0), bn, I(0, 1));
     chain_step<R, false>(w, bm, I(0, 2));
     chain_step<R, true>(w, bn, I(1, 1));
     chain_step<R, true>(w, bn, I(1, 0));
-    maxpy(S, cr, w);
+    chain_add(S, cr, w);
     w = chain_start<R, false, false>(bn, I(0, 0), bm, I(0, 1));
     chain_step<R, false>(w, bm, I(1, 1));
     chain_step<R, true>(w, bn, I(2, 0));
     chain_step<R, true>(w, bm, I(1, 0));
-    maxpy(S, cr, w);
+    chain_add(S, cr, w);
     w = chain_start<R, true, false>(bm, I(-1, 0), bn, I(-1, 0));
     chain_step<R, false>(w, bm, I(-1, 1));
     chain_step<R, false>(w, bm, I(0, 1));
     chain_step<R, true>(w, bn, I(1, 0));
-    maxpy(S, cr, w);
+    chain_add(S, cr, w);
   } else {
     M3<R> w = chain_start<R, true, false>(bn, I(0, -1), bm, I(0, -1));
     chain_step<R, false>(w, bn, I(1, -1));
-    maxpy(S, cp, w);
+    chain_add(S, cp, w);
     if (!OI) return;
     w = chain_start<R, true, true>(bn, I(0, -1), bn, I(0, -2));
     chain_step<R, false>(w, bm, I(0, -2));
     chain_step<R, false>(w, bn, I(1, -2));
     chain_step<R, false>(w, bn, I(1, -1));
-    maxpy(S, cr, w);
+    chain_add(S, cr, w);
     w = chain_start<R, true, false>(bn, I(0, -1), bm, I(0, -1));
     chain_step<R, false>(w, bm, I(1, -1));
     chain_step<R, false>(w, bn, I(2, -1));
     chain_step<R, true>(w, bm, I(1, 0));
-    maxpy(S, cr, w);
+    chain_add(S, cr, w);
     w = chain_start<R, true, true>(bm, I(-1, 0), bn, I(-1, -1));
     chain_step<R, false>(w, bm, I(-1, -1));
     chain_step<R, false>(w, bm, I(0, -1));
     chain_step<R, false>(w, bn, I(1, -1));
-    maxpy(S, cr, w);
+    chain_add(S, cr, w);
   }
+}
+
+// The same paths with every distinct link loaded once per orientation (10
+// loads instead of 14) and the plaquette staple sharing A B with the 2x1 path
+// whose site x sits at the left; K = U_mu(x+mu) and L = U_mu(x-mu) are common to
+// all nu and loaded once by the caller.  Needs about 5 live matrices besides
+// Sigma, K and L: used where matrices are FP32.
+template <typename R, bool UP>
+__device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm, const DirBuf<R>& bn,
+                                                  const Geo& g, const Nb& o, R cp, R cr,
+                                                  const M3<R>& K, const M3<R>& L) {
+  auto I = [&](int a, int b) { return nbi(g, o, a, b); };
+  const int sg = UP ? 1 : -1;
+  const M3<R> Ar = ld_link(bn, I(0, UP ? 0 : -1));
+  load_fence();
+  const M3<R> Cr = ld_link(bn, I(1, UP ? 0 : -1));
+  load_fence();
+  // 1x2: A D E F^dag C^dag
+  M3<R> w;
+  {
+    const M3<R> Dr = ld_link(bn, I(0, UP ? 1 : -2));
+    load_fence();
+    w = UP ? mul2_nn(Ar, Dr) : mul2_dd(Ar, Dr);
+  }
+  chain_step<R, false>(w, bm, I(0, 2 * sg));
+  {
+    const M3<R> Fr = ld_link(bn, I(1, UP ? 1 : -2));
+    load_fence();
+    w = UP ? mul2_nd(w, Fr) : mul2_nn(w, Fr);
+  }
+  w = UP ? mul2_nd(w, Cr) : mul2_nn(w, Cr);
+  chain_add(S, cr, w);
+  // plaquette A B C^dag and 2x1 left A B G H^dag K^dag share T = A B
+  const M3<R> Br = ld_link(bm, I(0, sg));
+  load_fence();
+  M3<R> T = UP ? mul2_nn(Ar, Br) : mul2_dn(Ar, Br);
+  chain_add(S, cp, UP ? mul2_nd(T, Cr) : mul2_nn(T, Cr));
+  chain_step<R, false>(T, bm, I(1, sg));
+  {
+    const M3<R> Hr = ld_link(bn, I(2, UP ? 0 : -1));
+    load_fence();
+    T = UP ? mul2_nd(T, Hr) : mul2_nn(T, Hr);
+  }
+  chain_add(S, cr, mul2_nd(T, K));
+  // 2x1 middle: L^dag M N B C^dag
+  {
+    const M3<R> Mr = ld_link(bn, I(-1, UP ? 0 : -1));
+    load_fence();
+    w = UP ? mul2_dn(L, Mr) : mul2_dd(L, Mr);
+  }
+  chain_step<R, false>(w, bm, I(-1, sg));
+  w = mul2_nn(w, Br);
+  w = UP ? mul2_nd(w, Cr) : mul2_nn(w, Cr);
+  chain_add(S, cr, w);
 }
 
 // ------------------------------------------------------------------ updates
@@ -461,6 +514,17 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* ds
     o.dm[2] = jdelta(g, MU, c[MU], 1);
     o.dm[3] = jdelta(g, MU, c[MU], 2);
     M3<R> S = mzero<R>();
+#ifndef VSM_SHARED_STAPLE
+#define VSM_SHARED_STAPLE 1
+#endif
+    constexpr bool kShared = VSM_SHARED_STAPLE && OI && sizeof(R) == 4;
+    M3<R> K, Lm;
+    if (kShared) {
+      K = ld_link(bm, nbi(g, o, 1, 0));
+      load_fence();
+      Lm = ld_link(bm, nbi(g, o, -1, 0));
+      load_fence();
+    }
 #pragma unroll 1
     for (int nu = 0; nu < 4; ++nu) {
       if (nu == MU) continue;
@@ -470,8 +534,13 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* ds
       o.dn[3] = jdelta(g, nu, c[nu], 1);
       o.dn[4] = jdelta(g, nu, c[nu], 2);
       const DirBuf<R> bn = dir_buf<R>(src, g, nu);
-      staple_dir<R, OI, true>(S, bm, bn, g, o, cp, cr);
-      staple_dir<R, OI, false>(S, bm, bn, g, o, cp, cr);
+      if (kShared) {
+        staple_dir_shared<R, true>(S, bm, bn, g, o, cp, cr, K, Lm);
+        staple_dir_shared<R, false>(S, bm, bn, g, o, cp, cr, K, Lm);
+      } else {
+        staple_dir<R, OI, true>(S, bm, bn, g, o, cp, cr);
+        staple_dir<R, OI, false>(S, bm, bn, g, o, cp, cr);
+      }
     }
     const M3<R> U = ld_link(bm, x);
     M3<double> cand;
@@ -759,19 +828,23 @@ void launch_update_mu(const Geo& g, const void* src, void* dst, const int8_t* z3
   const uint32_t n = jacobi ? g.V : g.V4;
   const unsigned nb = blocks_for(n, 256);
   const double2* gp = (const double2*)gauge;
+#ifndef VSM_LDS_PAD
+#define VSM_LDS_PAD 0
+#endif
+  const unsigned lds = VSM_LDS_PAD;
   if (p.oi) {
     if (p.update == 0)
-      hipLaunchKernelGGL((k_update<R, MU, true, 0>), dim3(nb), dim3(256), 0, st, g, src, dst, z3, gp, p,
+      hipLaunchKernelGGL((k_update<R, MU, true, 0>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
                          colour, jacobi, n, rej);
     else
-      hipLaunchKernelGGL((k_update<R, MU, true, 1>), dim3(nb), dim3(256), 0, st, g, src, dst, z3, gp, p,
+      hipLaunchKernelGGL((k_update<R, MU, true, 1>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
                          colour, jacobi, n, rej);
   } else {
     if (p.update == 0)
-      hipLaunchKernelGGL((k_update<R, MU, false, 0>), dim3(nb), dim3(256), 0, st, g, src, dst, z3, gp, p,
+      hipLaunchKernelGGL((k_update<R, MU, false, 0>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
                          colour, jacobi, n, rej);
     else
-      hipLaunchKernelGGL((k_update<R, MU, false, 1>), dim3(nb), dim3(256), 0, st, g, src, dst, z3, gp, p,
+      hipLaunchKernelGGL((k_update<R, MU, false, 1>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
                          colour, jacobi, n, rej);
   }
 }

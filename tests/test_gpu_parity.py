@@ -75,14 +75,19 @@ def test_centrifuge_matches_oracle(dims):
 
 
 def test_set_get_roundtrip():
+    """Links are stored as rows 0 and 1; row 2 comes back as conj(row0 x row1)."""
     dims = (4, 4, 4, 8)
     U = _haar(dims, 5)
     f = _field(dims)
     api.set_links(f, torch.from_numpy(U))
-    np.testing.assert_array_equal(_links(f), U)
+    got = _links(f)
+    np.testing.assert_array_equal(got[..., :2, :], U[..., :2, :])
+    assert np.abs(got - U).max() < 1e-15
     g = _field(dims, "fp32_bulk")
     api.set_links(g, torch.from_numpy(U))
-    np.testing.assert_array_equal(_links(g), U.astype(np.complex64).astype(np.complex128))
+    got32 = _links(g)
+    np.testing.assert_array_equal(got32[..., :2, :], U[..., :2, :].astype(np.complex64))
+    assert np.abs(got32 - U).max() < 5e-7
 
 
 @pytest.mark.parametrize("kind", ["centrifuged", "haar"])
@@ -204,8 +209,11 @@ def test_maxretr_annealed_random_gauge(alpha, eps):
     assert np.abs(_links(f) - U).max() < 1e-11
 
 
-def test_centre_field_unchanged_bit_identical():
-    """Sec. II.A: a centre field has Q = 0 and is left unchanged by stout."""
+def test_centre_field_unchanged():
+    """Sec. II.A: a centre field has Q = 0 and is left unchanged by stout.  Row 2
+    of the stored link is rebuilt from rows 0 and 1, one rounding away from the
+    exact centre element, so Q is ~1e-15 instead of 0 and the field moves by
+    rounding only: within 1e-14 after five sweeps."""
     dims = (8, 8, 8, 8)
     n = fieldgen.z3_vortex_charges(dims, 0.2, 41)
     f = _field(dims)
@@ -213,7 +221,7 @@ def test_centre_field_unchanged_bit_identical():
     before = _links(f)
     api.smooth(f, 3, 0.1, -0.25, order="annealed", vp=True)
     api.smooth(f, 2, 0.1, 1.0, order="jacobi")
-    np.testing.assert_array_equal(_links(f), before)
+    np.testing.assert_allclose(_links(f), before, atol=1e-14, rtol=0)
 
 
 def test_deterministic_and_resumable():
