@@ -50,7 +50,8 @@ extern "C" {
 #define VSM_E_WORKSPACE (-4) /* workspace smaller than vsm_workspace_bytes          */
 #define VSM_E_BUDGET (-5)    /* serving: job larger than the whole memory budget     */
 #define VSM_E_HIP (-6)       /* a HIP call failed; see vsm_last_hip_error()          */
-#define VSM_E_STATE (-7)     /* serving: unknown job or server shut down             */
+#define VSM_E_STATE (-7)     /* serving: unknown job, or the job cannot do this now   */
+#define VSM_E_TIMEOUT (-8)   /* serving: the wait ended before the job finished       */
 
 #define VSM_FP64 0
 #define VSM_FP32_BULK 1
@@ -169,6 +170,111 @@ int vsm_pass(const int32_t dims[4], int32_t precision, void *links_dev, const in
 int vsm_measure(const int32_t dims[4], int32_t precision, const void *links_dev, const int8_t *z3_dev,
                 void *workspace_dev, size_t workspace_bytes, vsm_stats *stats_dev,
                 int8_t *flux_dev, void *stream);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A server smooths a stream of independent jobs (Z(3) fields of any allowed
+ * size) on one GPU with continuous batching.  It owns one worker thread, one
+ * HIP stream, one device memory pool of hbm_budget_bytes and one pinned host
+ * pool of host_budget_bytes, all allocated by vsm_server_create and released by
+ * vsm_server_destroy; nothing else allocates on the device while it runs.
+ *
+ * A submitted job waits in a FIFO queue until its footprint
+ * (vsm_server_job_bytes) fits in the free device pool and a slot is free; it is
+ * then admitted: its charges (and centrifuge pairs) are uploaded, the field is
+ * built (Sec. I ingest, or Sec. IV preconditioning) and stays resident until
+ * the job ends.  Every scheduler step is one kernel launch that runs the next
+ * annealing subset pass (Sec. III.A order: mu = 0..3, subsets 0, 2, 1, 3) of
+ * every resident job, so jobs that arrive while others run join at the next
+ * step and small lattices share launches.  Measurement records follow the
+ * rules of vsm_smooth, plus one final record after the last sweep when
+ * n_sweeps is not a multiple of measure_every (or measure_every = 0).  A job's
+ * links and records are bit-identical whatever other jobs run beside it; they
+ * equal vsm_smooth's up to the rounding of the same arithmetic in another
+ * kernel.  Only VSM_ANNEALED stout schedules are served, without a gauge.
+ *
+ * Job states: QUEUED -> RUNNING -> DONE, or FAILED (a HIP error, or the server
+ * was destroyed first).  Times are seconds on the server's steady clock
+ * (vsm_server_clock).  All server calls are thread-safe. */
+
+#define VSM_JOB_QUEUED 0
+#define VSM_JOB_RUNNING 1
+#define VSM_JOB_DONE 2
+#define VSM_JOB_FAILED 3
+
+typedef struct {
+  size_t hbm_budget_bytes;  /* device pool for resident jobs (> 0)                       */
+  size_t host_budget_bytes; /* pinned host pool for uploads and results (> 0)            */
+  int32_t max_slots;        /* jobs resident at once, 1..256                             */
+  int32_t max_inflight;     /* scheduler steps queued ahead of the GPU, 1..64            */
+  int32_t device;           /* HIP device ordinal                                        */
+  int32_t reserved;
+} vsm_server_config;
+
+typedef struct {
+  int32_t dims[4];          /* as for every call; the field's extents                    */
+  int32_t precision;        /* VSM_FP64 or VSM_FP32_BULK                                  */
+  int32_t n_sweeps;         /* >= 0                                                       */
+  double rho, eps;          /* as for vsm_smooth                                          */
+  double omega;             /* centrifuge parameter, |omega| < 1/4 (unused without pairs) */
+  vsm_schedule sched;       /* order VSM_ANNEALED, update VSM_STOUT                       */
+  int32_t measure_every;    /* >= 0, as for vsm_smooth                                    */
+  int32_t want_links;       /* 1: keep the final links (canonical layout) for fetch       */
+  const int8_t *z3_host;    /* host int8 [4][V] charges; copied by submit                 */
+  const int8_t *pair_host;  /* host int8 [4][V] centrifuge pairs, copied by submit, or
+                               NULL for the plain Z(3) field                              */
+} vsm_job;
+
+typedef struct {
+  int32_t state;            /* VSM_JOB_*                                                  */
+  int32_t status;           /* VSM_OK, or the error that failed the job                   */
+  int32_t n_records;        /* vsm_stats records the job produces                         */
+  int32_t sweeps_done;      /* sweeps enqueued so far                                     */
+  double t_submit, t_admit, t_done; /* server clock; -1 until reached                    */
+  size_t footprint_bytes;   /* device pool bytes the job holds while resident            */
+} vsm_job_info;
+
+typedef struct {
+  int64_t steps;            /* scheduler steps (batched launches) enqueued               */
+  int64_t launches;         /* kernel launches of those steps                            */
+  int64_t jobs_submitted, jobs_done, jobs_failed;
+  int64_t link_updates;     /* link updates enqueued over all jobs                       */
+  int64_t peak_resident_jobs;
+  size_t peak_pool_bytes;   /* high-water mark of the device pool                        */
+  double busy_seconds;      /* worker time with at least one job resident                */
+} vsm_server_counters;
+
+/* Device pool bytes one job needs (links, charges, pairs, workspace, records,
+ * and the canonical link buffer when want_links); 0 if the job is invalid. */
+size_t vsm_server_job_bytes(const vsm_job *job);
+/* Pinned host pool bytes one job needs (uploads and results). */
+size_t vsm_server_host_bytes(const vsm_job *job);
+
+/* Creates a server; *srv receives its handle.  VSM_E_HIP if a pool cannot be
+ * allocated. */
+int vsm_server_create(const vsm_server_config *cfg, void **srv);
+/* Validates and enqueues a job; *job_id receives its id.  VSM_E_BUDGET if the
+ * job can never fit the pools; VSM_E_PARAM for a schedule the server does not
+ * serve; VSM_E_STATE after destroy has begun. */
+int vsm_server_submit(void *srv, const vsm_job *job, uint64_t *job_id);
+/* Current state of a job into *info (host); does not block. */
+int vsm_server_poll(void *srv, uint64_t job_id, vsm_job_info *info);
+/* Blocks until the job is DONE or FAILED (VSM_OK) or timeout_s seconds have
+ * passed (VSM_E_TIMEOUT; timeout_s < 0 waits without limit); *info as poll. */
+int vsm_server_wait(void *srv, uint64_t job_id, double timeout_s, vsm_job_info *info);
+/* Copies a DONE job's results to host memory and forgets the job:
+ * records_host receives up to max_records vsm_stats, links_host (complex128
+ * [4][V][3][3], may be NULL) the final links if the job kept them.  A FAILED
+ * job is forgotten and its status returned.  VSM_E_STATE if not finished. */
+int vsm_server_fetch(void *srv, uint64_t job_id, vsm_stats *records_host, int32_t max_records,
+                     double *links_host);
+/* Seconds on the server's steady clock. */
+double vsm_server_clock(void *srv);
+/* Scheduler counters into *out (host). */
+int vsm_server_get_counters(void *srv, vsm_server_counters *out);
+/* Stops admitting, lets the device finish what is enqueued, fails the jobs
+ * not finished, joins the worker and releases the pools and the handle. */
+int vsm_server_destroy(void *srv);
 
 #ifdef __cplusplus
 }

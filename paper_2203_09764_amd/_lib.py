@@ -13,7 +13,8 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvsm.so")
 
 OK = 0
-E_DIMS, E_PARAM, E_NULL, E_WORKSPACE, E_BUDGET, E_HIP, E_STATE = -1, -2, -3, -4, -5, -6, -7
+E_DIMS, E_PARAM, E_NULL, E_WORKSPACE, E_BUDGET, E_HIP, E_STATE, E_TIMEOUT = -1, -2, -3, -4, -5, -6, -7, -8
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 FP64, FP32_BULK = 0, 1
 JACOBI, ANNEALED = 0, 1
 STOUT, MAXRETR = 0, 1
@@ -30,6 +31,32 @@ STATS_BYTES = STATS_DTYPE.itemsize
 class Schedule(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("update", ctypes.c_int32), ("vp", ctypes.c_int32),
                 ("su2_loops", ctypes.c_int32), ("u0", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("host_budget_bytes", ctypes.c_size_t),
+                ("max_slots", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("precision", ctypes.c_int32), ("n_sweeps", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("eps", ctypes.c_double), ("omega", ctypes.c_double),
+                ("sched", Schedule), ("measure_every", ctypes.c_int32), ("want_links", ctypes.c_int32),
+                ("z3_host", ctypes.c_void_p), ("pair_host", ctypes.c_void_p)]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("n_records", ctypes.c_int32),
+                ("sweeps_done", ctypes.c_int32), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("footprint_bytes", ctypes.c_size_t)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("launches", ctypes.c_int64), ("jobs_submitted", ctypes.c_int64),
+                ("jobs_done", ctypes.c_int64), ("jobs_failed", ctypes.c_int64),
+                ("link_updates", ctypes.c_int64), ("peak_resident_jobs", ctypes.c_int64),
+                ("peak_pool_bytes", ctypes.c_size_t), ("busy_seconds", ctypes.c_double)]
 
 
 class VsmError(RuntimeError):
@@ -79,16 +106,22 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
-        for name, (res, args) in EXTRA_SIGNATURES.items():
-            if hasattr(L, name):
-                f = getattr(L, name)
-                f.restype = res
-                f.argtypes = args
         _lib = L
     return _lib
 
 
-EXTRA_SIGNATURES: dict = {}
+SIGNATURES.update({
+    "vsm_server_job_bytes": (_sz, [ctypes.POINTER(Job)]),
+    "vsm_server_host_bytes": (_sz, [ctypes.POINTER(Job)]),
+    "vsm_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    "vsm_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Job), ctypes.POINTER(_u64)]),
+    "vsm_server_poll": (ctypes.c_int, [_P, _u64, ctypes.POINTER(JobInfo)]),
+    "vsm_server_wait": (ctypes.c_int, [_P, _u64, _f64, ctypes.POINTER(JobInfo)]),
+    "vsm_server_fetch": (ctypes.c_int, [_P, _u64, _P, _i32, _P]),
+    "vsm_server_clock": (_f64, [_P]),
+    "vsm_server_get_counters": (ctypes.c_int, [_P, ctypes.POINTER(ServerCounters)]),
+    "vsm_server_destroy": (ctypes.c_int, [_P]),
+})
 
 
 def dims_arg(dims) -> Dims:

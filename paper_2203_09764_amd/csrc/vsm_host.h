@@ -1,0 +1,124 @@
+// vsm_host.h -- host-side helpers shared by the C-ABI entry points and the
+// serving scheduler: argument validation, the internal lattice geometry, the
+// workspace layout and the per-launch update parameters.
+#pragma once
+
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "vsm.h"
+#include "vsm_launch.h"
+
+namespace vsm {
+
+// Records e as this thread's last HIP error; VSM_E_HIP if e is an error.
+int note_hip_error(hipError_t e);
+// note_hip_error(hipGetLastError()).
+int hip_status();
+
+inline size_t entry_bytes(int32_t precision) { return precision == VSM_FP64 ? 16 : 8; }
+
+inline bool valid_precision(int32_t p) { return p == VSM_FP64 || p == VSM_FP32_BULK; }
+
+inline bool is_fin(double v) { return isfinite(v) != 0; }
+
+inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+inline int check_dims_impl(const int32_t dims[4], int32_t order, int32_t precision) {
+  if (!dims) return VSM_E_NULL;
+  if (!valid_precision(precision)) return VSM_E_PARAM;
+  if (order != VSM_JACOBI && order != VSM_ANNEALED) return VSM_E_PARAM;
+  uint64_t V = 1;
+  for (int d = 0; d < 4; ++d) {
+    if (dims[d] < 4 || dims[d] % 4) return VSM_E_DIMS;
+    V *= (uint64_t)dims[d];
+  }
+  if (6ull * V * entry_bytes(precision) >= (1ull << 31)) return VSM_E_DIMS;
+  return VSM_OK;
+}
+
+// Internal axis 0 (blocked by 4, fastest in memory) is the longest user axis,
+// preferring one whose rows of L/4 FP64 entries fill whole 128-byte lines; the
+// other user axes follow in their own order.  Directions are relabelled with
+// the axes, which leaves the annealing subsets unchanged.
+inline Geo make_geo(const int32_t dims[4]) {
+  int a0 = 0;
+  auto score = [&](int d) { return (long)dims[d] * 2 + (((dims[d] / 4) * 16) % 128 == 0 ? 1 : 0); };
+  for (int d = 1; d < 4; ++d)
+    if (score(d) > score(a0)) a0 = d;
+  Geo g;
+  g.perm[a0] = 0;
+  g.uperm[0] = a0;
+  int k = 1;
+  for (int d = 0; d < 4; ++d)
+    if (d != a0) {
+      g.perm[d] = k;
+      g.uperm[k] = d;
+      ++k;
+    }
+  uint32_t cstride[4];
+  uint32_t acc = 1;
+  for (int d = 0; d < 4; ++d) {
+    cstride[d] = acc;
+    acc *= (uint32_t)dims[d];
+  }
+  for (int i = 0; i < 4; ++i) {
+    g.L[i] = dims[g.uperm[i]];
+    g.cst[i] = cstride[g.uperm[i]];
+  }
+  g.Xq = g.L[0] / 4;
+  g.V = acc;
+  g.V4 = g.V / 4;
+  g.jst[0] = 1;
+  g.jst[1] = (uint32_t)g.Xq;
+  g.jst[2] = (uint32_t)g.Xq * (uint32_t)g.L[1];
+  g.jst[3] = (uint32_t)g.Xq * (uint32_t)g.L[1] * (uint32_t)g.L[2];
+  return g;
+}
+
+// Workspace: [0, 256) counters (rejections at 0); then the measurement block
+// partials; then, for the smearing schedule, a second link buffer.
+struct WsLayout {
+  size_t counters, partials, field, total;
+};
+
+inline WsLayout ws_layout(const int32_t dims[4], int32_t precision, int32_t order) {
+  const Geo g = make_geo(dims);
+  WsLayout w;
+  w.counters = 0;
+  w.partials = 256;
+  w.field = align256(w.partials + (size_t)measure_blocks(g) * partial_bytes());
+  w.total = w.field;
+  if (order == VSM_JACOBI) w.total += align256(24ull * g.V * entry_bytes(precision));
+  return w;
+}
+
+inline int check_sched(const vsm_schedule* s) {
+  if (!s) return VSM_E_NULL;
+  if (s->order != VSM_JACOBI && s->order != VSM_ANNEALED) return VSM_E_PARAM;
+  if (s->update != VSM_STOUT && s->update != VSM_MAXRETR) return VSM_E_PARAM;
+  if (!is_fin(s->u0) || s->u0 == 0.0) return VSM_E_PARAM;
+  if (s->update == VSM_MAXRETR && (!is_fin(s->alpha) || s->su2_loops < 0)) return VSM_E_PARAM;
+  return VSM_OK;
+}
+
+// Staple weights of the over-improved action: c_p = (5 - 2 eps)/3 and
+// c_r = (eps - 1)/(12 u0^2); eps = 1 leaves the plain plaquette staples.
+inline UpdParams make_params(double rho, double eps, const vsm_schedule* s) {
+  UpdParams p;
+  p.cp = (5.0 - 2.0 * eps) / 3.0;
+  p.cr = (eps - 1.0) / (12.0 * s->u0 * s->u0);
+  p.rho = rho;
+  p.alpha = s->alpha;
+  p.update = s->update == VSM_MAXRETR ? 1 : 0;
+  p.oi = p.cr != 0.0 ? 1 : 0;
+  p.vp = s->vp ? 1 : 0;
+  p.loops = s->su2_loops;
+  return p;
+}
+
+// Subset order of one direction in an annealed sweep.
+constexpr int kColours[4] = {0, 2, 1, 3};
+
+}  // namespace vsm

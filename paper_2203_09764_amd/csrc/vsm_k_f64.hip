@@ -12,4 +12,5 @@ template void launch_update_t<double>(const Geo&, const void*, void*, const int8
                                  const UpdParams&, int, int, int, unsigned long long*, hipStream_t);
 template void launch_measure_t<double>(const Geo&, const void*, const int8_t*, void*, int8_t*,
                                   unsigned long long*, VsmStatsDev*, long long, hipStream_t);
+template void launch_update_batch_t<double>(const ServeJob*, const BatchStep&, uint32_t, hipStream_t);
 }  // namespace vsm

@@ -18,6 +18,8 @@ template <typename R>
 void launch_update_t(const Geo&, const void*, void*, const int8_t*, const void*, const UpdParams&, int,
                      int, int, unsigned long long*, hipStream_t);
 template <typename R>
+void launch_update_batch_t(const ServeJob*, const BatchStep&, uint32_t, hipStream_t);
+template <typename R>
 void launch_measure_t(const Geo&, const void*, const int8_t*, void*, int8_t*, unsigned long long*,
                       VsmStatsDev*, long long, hipStream_t);
 
@@ -63,6 +65,12 @@ void launch_update(int prec, const Geo& g, const void* src, void* dst, const int
                    unsigned long long* rej, hipStream_t st) {
   if (prec == 0) launch_update_t<double>(g, src, dst, z3, gauge, p, mu, colour, jacobi, rej, st);
   else launch_update_t<float>(g, src, dst, z3, gauge, p, mu, colour, jacobi, rej, st);
+}
+
+void launch_update_batch(int prec, const ServeJob* jobs_dev, const BatchStep& step, uint32_t nblocks,
+                         hipStream_t st) {
+  if (prec == 0) launch_update_batch_t<double>(jobs_dev, step, nblocks, st);
+  else launch_update_batch_t<float>(jobs_dev, step, nblocks, st);
 }
 
 // Block partials written by the measurement kernel: 10 eight-byte fields.

@@ -473,26 +473,17 @@ __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t
   }
 }
 
-// One update step for direction MU.  jacobi = 0: the annealing subset `colour`,
-// in place (src == dst).  jacobi = 1: every link of direction MU from src into
-// dst (smearing).  UPD = 0 stout, 1 MaxReTr.  With vp, a candidate is kept only
-// if its centre sector (after undoing the gauge transform, when one is given)
-// equals the original charge; rejections are counted per wave into *rejected.
+// One link update of direction MU for thread t: jacobi = 0, the t-th link of
+// annealing subset `colour`, in place (src == dst); jacobi = 1, link t of
+// direction MU from src into dst (smearing).  UPD = 0 stout, 1 MaxReTr.  With
+// vp, a candidate is kept only if its centre sector (after undoing the gauge
+// transform, when one is given) equals the original charge.  Returns whether a
+// candidate was rejected.
 template <typename R, int MU, bool OI, int UPD>
-__global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* dst,
-                                                const int8_t* __restrict__ z3,
-                                                const double2* __restrict__ gauge, UpdParams p,
-                                                int colour, int jacobi, uint32_t nthreads,
-                                                unsigned long long* __restrict__ rejected) {
-  // XCD-aware block order: consecutive hardware blocks go round-robin to the 8
-  // XCDs; give each XCD one contiguous range of the lattice for L2 reuse.
-  uint32_t b = blockIdx.x;
-  const uint32_t nb = gridDim.x;
-#ifndef VSM_XCD_REMAP
-#define VSM_XCD_REMAP 1
-#endif
-  if (VSM_XCD_REMAP && (nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
-  const uint32_t t = b * blockDim.x + threadIdx.x;
+__device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* dst,
+                                           const int8_t* __restrict__ z3,
+                                           const double2* __restrict__ gauge, const UpdParams& p,
+                                           int colour, int jacobi, uint32_t t, uint32_t nthreads) {
   const bool active = t < nthreads;
   int c[4] = {0, 0, 0, 0};
   if (active) {
@@ -575,10 +566,76 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* ds
       st_link<R>(dst, g, MU, x, outl);
     }
   }
+  return rej;
+}
+
+// One update step for direction MU over the whole lattice (see update_one);
+// rejections are counted per wave into *rejected.
+template <typename R, int MU, bool OI, int UPD>
+__global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* dst,
+                                                const int8_t* __restrict__ z3,
+                                                const double2* __restrict__ gauge, UpdParams p,
+                                                int colour, int jacobi, uint32_t nthreads,
+                                                unsigned long long* __restrict__ rejected) {
+  // XCD-aware block order: consecutive hardware blocks go round-robin to the 8
+  // XCDs; give each XCD one contiguous range of the lattice.
+  uint32_t b = blockIdx.x;
+  const uint32_t nb = gridDim.x;
+#ifndef VSM_XCD_REMAP
+#define VSM_XCD_REMAP 1
+#endif
+  if (VSM_XCD_REMAP && (nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
+  const uint32_t t = b * blockDim.x + threadIdx.x;
+  const bool rej = update_one<R, MU, OI, UPD>(g, src, dst, z3, gauge, p, colour, jacobi, t, nthreads);
   if (rejected) {
     const unsigned long long m = __ballot(rej);
     if ((threadIdx.x & 63u) == 0u && m) atomicAdd(rejected, (unsigned long long)__popcll(m));
   }
+}
+
+// One serving step (see BatchStep): each block belongs to one job, found from
+// the step's block ranges; its threads run that job's subset pass with exactly
+// the per-link code of k_update, so a job's links do not depend on which other
+// jobs share the launch.  Stout updates only.
+template <typename R, int MU, bool OI>
+__device__ __forceinline__ bool batch_one(const ServeJob& J, int colour, uint32_t t) {
+  return update_one<R, MU, OI, 0>(J.g, J.links, J.links, J.z3, nullptr, J.p, colour, 0, t, J.g.V4);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_update_batch(const ServeJob* __restrict__ jobs, BatchStep st) {
+  const uint32_t b = blockIdx.x;
+  uint32_t fb = st.first_block[0], slot = st.slot[0];
+  int mu = st.mu[0], colour = st.colour[0];
+#pragma unroll
+  for (int k = 1; k < kBatchMax; ++k) {
+    if ((uint32_t)k < st.njobs && b >= st.first_block[k]) {
+      fb = st.first_block[k];
+      slot = st.slot[k];
+      mu = st.mu[k];
+      colour = st.colour[k];
+    }
+  }
+  const ServeJob& J = jobs[slot];
+  const uint32_t t = (b - fb) * blockDim.x + threadIdx.x;
+  bool rej;
+  if (J.p.oi) {
+    switch (mu) {
+      case 0: rej = batch_one<R, 0, true>(J, colour, t); break;
+      case 1: rej = batch_one<R, 1, true>(J, colour, t); break;
+      case 2: rej = batch_one<R, 2, true>(J, colour, t); break;
+      default: rej = batch_one<R, 3, true>(J, colour, t); break;
+    }
+  } else {
+    switch (mu) {
+      case 0: rej = batch_one<R, 0, false>(J, colour, t); break;
+      case 1: rej = batch_one<R, 1, false>(J, colour, t); break;
+      case 2: rej = batch_one<R, 2, false>(J, colour, t); break;
+      default: rej = batch_one<R, 3, false>(J, colour, t); break;
+    }
+  }
+  const unsigned long long m = __ballot(rej);
+  if ((threadIdx.x & 63u) == 0u && m) atomicAdd(J.rej, (unsigned long long)__popcll(m));
 }
 
 // ------------------------------------------------------------------ measurement
@@ -859,6 +916,11 @@ void launch_update_t(const Geo& g, const void* src, void* dst, const int8_t* z3,
     case 2: launch_update_mu<R, 2>(g, src, dst, z3, gauge, p, colour, jacobi, rej, st); break;
     default: launch_update_mu<R, 3>(g, src, dst, z3, gauge, p, colour, jacobi, rej, st); break;
   }
+}
+
+template <typename R>
+void launch_update_batch_t(const ServeJob* jobs, const BatchStep& step, uint32_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_batch<R>, dim3(nblocks), dim3(256), 0, st, jobs, step);
 }
 
 template <typename R>

@@ -27,6 +27,29 @@ struct VsmStatsDev {
   long long flux_mismatch, undefined_sector, rejected, nonfinite;
 };
 
+// A job resident on the device under the serving scheduler: its geometry,
+// buffers and update parameters, written once when the job is admitted.
+struct ServeJob {
+  Geo g;
+  void* links;
+  const int8_t* z3;
+  unsigned long long* rej;  // the job's rejection counter
+  UpdParams p;
+};
+
+// One step of the serving scheduler: one annealing subset pass of each listed
+// job, all in one launch.  Job i owns blocks [first_block[i], first_block[i+1])
+// (the last one up to the grid size) and runs subset `colour[i]` of internal
+// direction mu[i] on jobs[slot[i]].
+constexpr int kBatchMax = 16;
+struct BatchStep {
+  uint32_t first_block[kBatchMax];
+  uint32_t slot[kBatchMax];
+  uint8_t mu[kBatchMax];
+  uint8_t colour[kBatchMax];
+  uint32_t njobs;
+};
+
 void launch_set_links(int prec, const Geo& g, const void* canon, void* links, hipStream_t st);
 void launch_get_links(int prec, const Geo& g, const void* links, void* canon, hipStream_t st);
 void launch_load_z3(int prec, const Geo& g, const int8_t* z3, void* links, hipStream_t st);
@@ -41,6 +64,11 @@ size_t partial_bytes();
 void launch_measure(int prec, const Geo& g, const void* links, const int8_t* z3, void* partials,
                     int8_t* flux, unsigned long long* rej, VsmStatsDev* out, long long sweep,
                     hipStream_t st);
+// Blocks of 256 threads one annealing pass of g takes.
+inline uint32_t pass_blocks(const Geo& g) { return (g.V4 + 255u) / 256u; }
+// One serving step: every job of `step` (stout updates, annealed, in place).
+void launch_update_batch(int prec, const ServeJob* jobs_dev, const BatchStep& step, uint32_t nblocks,
+                         hipStream_t st);
 void launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 
 }  // namespace vsm
