@@ -540,10 +540,13 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
       moved = stout_candidate<R>(S, U, p.rho, cand);
     else
       moved = maxretr_candidate<R>(S, U, p.alpha, p.loops, cand);
-    const M3<R> cr_ = mconvert<R>(cand);
+    // the candidate exactly as a later load will see it: rows 0 and 1 rounded
+    // to the storage precision, row 2 rebuilt from them
+    M3<R> cr_ = mconvert<R>(cand);
+    rebuild_row2(cr_);
     bool accept = moved;
     if (moved && p.vp) {
-      // sector of the stored (rounded) candidate, evaluated in FP64
+      // sector of the stored candidate, evaluated in FP64 as the measurement does
       Cx<double> tr;
       if (gauge) {
         int cp1[4] = {c[0], c[1], c[2], c[3]};
