@@ -64,6 +64,8 @@ def lib():
             "ora_maxretr": (None, [P, P, i32, P]),
             "ora_update_link": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32,
                                                i32, i64, P, P]),
+            "ora_update_links": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32,
+                                                i64, P, P, P, P]),
             "ora_pass": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32, i32,
                                         i32, P]),
             "ora_smooth": (ctypes.c_int, [P, P, P, P, i32, i32, i32, i32, f64, f64, f64, f64,
@@ -183,6 +185,25 @@ def update_link(dims, links, n0, mu, site, *, gauge=None, update="stout", vp=Fal
                                  int(su2_loops), int(mu), int(site), _p(out), ctypes.byref(acc)),
            "update_link")
     return out, bool(acc.value)
+
+
+def update_links(dims, links, n0, mus, sites, *, gauge=None, update="stout", vp=False, rho=0.1,
+                 eps=1.0, u0=1.0, alpha=1.0, su2_loops=3):
+    """update_link for many (mu, site) pairs with one lattice set-up: returns
+    (complex128 [count, 3, 3], bool [count])."""
+    links = np.ascontiguousarray(links, dtype=np.complex128)
+    n0 = None if n0 is None else np.ascontiguousarray(n0, dtype=np.int8)
+    gauge = None if gauge is None else np.ascontiguousarray(gauge, dtype=np.complex128)
+    mus = np.ascontiguousarray(mus, dtype=np.int32)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    assert mus.shape == sites.shape and mus.ndim == 1
+    out = np.empty((len(mus), 3, 3), dtype=np.complex128)
+    acc = np.empty(len(mus), dtype=np.int32)
+    _check(lib().ora_update_links(_p(_dims(dims)), _p(links), _p(n0), _p(gauge), _upd(update),
+                                  int(bool(vp)), float(rho), float(eps), float(u0), float(alpha),
+                                  int(su2_loops), len(mus), _p(mus), _p(sites), _p(out), _p(acc)),
+           "update_links")
+    return out, acc.astype(bool)
 
 
 def anneal_pass(dims, links, n0, mu, colour, *, gauge=None, update="stout", vp=False, rho=0.1,

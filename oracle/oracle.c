@@ -557,6 +557,32 @@ int ora_update_link(const int32_t dims[4], const double *links, const int8_t *n0
   return ORA_OK;
 }
 
+int ora_update_links(const int32_t dims[4], const double *links, const int8_t *n0,
+                     const double *gauge, int32_t update, int32_t vp, double rho, double eps,
+                     double u0, double alpha, int32_t su2_loops, int64_t count, const int32_t *mus,
+                     const int64_t *sites, double *out, int32_t *accepted) {
+  if (!links || !out || !mus || !sites || (vp && !n0)) return ORA_E_NULL;
+  params pr = {update, vp, rho, eps, u0, alpha, su2_loops};
+  if (!check_params(&pr) || count < 0) return ORA_E_PARAM;
+  lattice g;
+  int rc = lat_init(&g, dims);
+  if (rc) return rc;
+  for (int64_t i = 0; i < count; ++i)
+    if (mus[i] < 0 || mus[i] > 3 || sites[i] < 0 || sites[i] >= g.V) {
+      lat_free(&g);
+      return ORA_E_PARAM;
+    }
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t i = 0; i < count; ++i) {
+    mat3 r;
+    const int acc = update_link(&g, links, n0, gauge, &pr, mus[i], sites[i], &r);
+    m_store(&r, out + 18 * i);
+    if (accepted) accepted[i] = acc;
+  }
+  lat_free(&g);
+  return ORA_OK;
+}
+
 /* ---------------------------------------------------------- schedules */
 
 /* Masked subset of the annealing schedule (Sec. III.A: annealing updates links

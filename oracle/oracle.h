@@ -68,6 +68,13 @@ int ora_update_link(const int32_t dims[4], const double *links, const int8_t *n0
                     const double *gauge, int32_t update, int32_t vp, double rho, double eps,
                     double u0, double alpha, int32_t su2_loops, int32_t mu, int64_t site,
                     double *out, int32_t *accepted);
+
+/* The same update for `count` links at once, (mus[i], sites[i]) -> out + 18 i
+ * (one call sets the lattice up once; for sampled checks of large lattices). */
+int ora_update_links(const int32_t dims[4], const double *links, const int8_t *n0,
+                     const double *gauge, int32_t update, int32_t vp, double rho, double eps,
+                     double u0, double alpha, int32_t su2_loops, int64_t count, const int32_t *mus,
+                     const int64_t *sites, double *out, int32_t *accepted);
 int ora_pass(const int32_t dims[4], double *links, const int8_t *n0, const double *gauge,
              int32_t update, int32_t vp, double rho, double eps, double u0, double alpha,
              int32_t su2_loops, int32_t mu, int32_t colour, int64_t *rejected);

@@ -1,0 +1,129 @@
+"""GPU parity at the full workload sizes (32^3 x 64 and 48^3 x 96), in the launch
+configuration the benchmark times, on sampled outputs the oracle computes one
+by one.
+
+* Centrifuge preconditioning (Sec. IV): the integer staple charges m of every
+  link bit-exact; sampled links within 1e-15.
+* One annealing subset pass (Sec. III.A, V, VI) of over-improved stout with
+  vortex preservation, from the preconditioned field and again from the field
+  after two more GPU sweeps: 512 sampled updated links against the oracle's
+  update of the same input within 1e-12 (FP64) and, for the FP32-bulk form,
+  within 2e-6; sampled links outside the subset unchanged, bit for bit.
+* Properties that hold at any size: no vortex lost, no non-finite link.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+import oracle as ora
+from paper_2203_09764_amd import api
+
+pytestmark = pytest.mark.gpu
+
+N_SAMPLES = 512
+
+
+def _coords(dims, s):
+    s = np.asarray(s, dtype=np.int64)
+    c = []
+    for L in dims:
+        c.append(s % L)
+        s = s // L
+    return c
+
+
+def _subset_sample(dims, mu, colour, k, seed):
+    """k canonical sites of annealing subset `colour` of direction mu:
+    (2 x_mu + sum_{nu != mu} x_nu) mod 4 = colour."""
+    rng = np.random.default_rng(seed)
+    V = fieldgen.volume(dims)
+    cand = rng.integers(0, V, size=16 * k)
+    c = _coords(dims, cand)
+    col = (sum(c) + c[mu]) % 4
+    pick = cand[col == colour][:k]
+    assert len(pick) == k
+    return pick
+
+
+def _other_sample(dims, mu, colour, k, seed):
+    """k links (direction, site) that the subset pass must leave alone."""
+    rng = np.random.default_rng(seed)
+    V = fieldgen.volume(dims)
+    mus = rng.integers(0, 4, size=4 * k)
+    sites = rng.integers(0, V, size=4 * k)
+    c = _coords(dims, sites)
+    col = (sum(c) + np.choose(mus, c)) % 4
+    keep = (mus != mu) | (col != colour)
+    return mus[keep][:k], sites[keep][:k]
+
+
+def _gather(f, mus, sites):
+    G = api.get_links(f)
+    idx_m = torch.as_tensor(np.asarray(mus, dtype=np.int64), device=G.device)
+    idx_s = torch.as_tensor(np.asarray(sites, dtype=np.int64), device=G.device)
+    out = G[idx_m, idx_s].cpu().numpy()
+    del G
+    return out
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("cfg", ["c2", "c4"])
+def test_full_size_fp64_passes_sampled(cfg):
+    c = fieldgen.CONFIGS[cfg]
+    dims, rho, eps = c["dims"], c["rho"], c["eps"]
+    print(f"[{cfg}] {dims}: generating the field", flush=True)
+    n = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
+    pairs = fieldgen.centrifuge_pairs(dims, c["pair_seed"])
+    f = api.Field(dims, "fp64", device=torch.device("cuda:0"), jacobi_workspace=False)
+    f.set_charges(n)
+    m = api.precondition(f, pairs, c["omega"], want_m=True).cpu().numpy()
+    U, m_ora = ora.centrifuge(dims, n, pairs, c["omega"], return_m=True)
+    np.testing.assert_array_equal(m, m_ora)
+    del m, m_ora
+    rng = np.random.default_rng(1)
+    V = fieldgen.volume(dims)
+    mus0, sites0 = rng.integers(0, 4, N_SAMPLES), rng.integers(0, V, N_SAMPLES)
+    assert np.abs(_gather(f, mus0, sites0) - U[mus0, sites0]).max() < 1e-15
+    for step, (mu, colour) in enumerate([(0, 0), (3, 3)]):
+        if step == 1:
+            # a later, non-diagonal field: two more sweeps on the GPU, read back
+            api.smooth(f, 2, rho, eps, order="annealed", vp=True)
+            del U
+            U = api.get_links(f).cpu().numpy()
+        print(f"[{cfg}] pass mu={mu} colour={colour}", flush=True)
+        sites = _subset_sample(dims, mu, colour, N_SAMPLES, 10 + step)
+        want, _ = ora.update_links(dims, U, n, np.full(N_SAMPLES, mu), sites, rho=rho, eps=eps, vp=True)
+        om, osites = _other_sample(dims, mu, colour, N_SAMPLES, 20 + step)
+        before = _gather(f, om, osites)  # the GPU's own links (row 2 as it rebuilds it)
+        api.anneal_pass(f, mu, colour, rho, eps, vp=True)
+        got = _gather(f, np.full(N_SAMPLES, mu), sites)
+        err = np.abs(got - want).max()
+        print(f"[{cfg}] pass mu={mu} colour={colour}: max link error {err:.2e}", flush=True)
+        assert err < 1e-12
+        np.testing.assert_array_equal(_gather(f, om, osites), before)
+    rec = api.stats_to_numpy(api.measure(f), 1)[0]
+    assert rec.flux_mismatch == 0 and rec.nonfinite == 0 and rec.undefined_sector == 0
+    assert rec.max_unitarity < 1e-14
+
+
+@pytest.mark.timeout(900)
+def test_full_size_fp32_bulk_first_pass_sampled():
+    c = fieldgen.CONFIGS["c4"]
+    dims, rho, eps = c["dims"], c["rho"], c["eps"]
+    n = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
+    pairs = fieldgen.centrifuge_pairs(dims, c["pair_seed"])
+    f = api.Field(dims, "fp32_bulk", device=torch.device("cuda:0"), jacobi_workspace=False)
+    f.set_charges(n)
+    api.precondition(f, pairs, c["omega"])
+    U = ora.centrifuge(dims, n, pairs, c["omega"])
+    mu, colour = 1, 2
+    sites = _subset_sample(dims, mu, colour, N_SAMPLES, 30)
+    want, _ = ora.update_links(dims, U, n, np.full(N_SAMPLES, mu), sites, rho=rho, eps=eps, vp=True)
+    api.anneal_pass(f, mu, colour, rho, eps, vp=True)
+    got = _gather(f, np.full(N_SAMPLES, mu), sites)
+    err = np.abs(got - want).max()
+    print(f"[c4 fp32_bulk] pass mu={mu} colour={colour}: max link error {err:.2e}", flush=True)
+    assert err < 2e-6
+    rec = api.stats_to_numpy(api.measure(f), 1)[0]
+    assert rec.flux_mismatch == 0 and rec.nonfinite == 0

@@ -643,3 +643,21 @@ def test_sweep_updates_every_link_once(ora, order):
         for s in range(0, fieldgen.volume(dims), 7):
             Q = ora.generator(ora.staple(dims, U, mu, s, eps=-0.25) @ U[mu, s].conj().T)
             np.testing.assert_allclose((W[mu, s] - U[mu, s]) / rho, Q @ U[mu, s], atol=2e-3)
+
+
+def test_batched_update_equals_the_pass(ora):
+    """update_links on the field before a subset pass gives, link for link, what
+    the pass stores (the links of one subset are independent, Sec. III.A)."""
+    dims = SMALL
+    U = _haar_field(dims, 311)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 312)
+    V = fieldgen.volume(dims)
+    mu, colour = 2, 1
+    sites = np.array([s for s in range(V) if ora.colour(dims, mu, s) == colour][::3])
+    out, acc = ora.update_links(dims, U, n, np.full(len(sites), mu), sites, rho=0.05, eps=-0.25, vp=True)
+    W = U.copy()
+    ora.anneal_pass(dims, W, n, mu, colour, rho=0.05, eps=-0.25, vp=True)
+    np.testing.assert_array_equal(out, W[mu, sites])
+    single, a1 = ora.update_link(dims, U, n, mu, int(sites[0]), rho=0.05, eps=-0.25, vp=True)
+    np.testing.assert_array_equal(single, out[0])
+    assert a1 == acc[0]
