@@ -240,7 +240,33 @@ struct Geo {
   uint32_t cst[4]; // canonical-index stride of internal axis d
   int perm[4];     // internal axis of user axis mu
   int uperm[4];    // user axis of internal axis d
+  int T1, T2;      // traversal tile: rows of axes 1 and 2 swept together through axis 3
 };
+
+// Axes 1..3 of the r-th row (x1, x2, x3) in traversal order (a row is the
+// run of x0 positions one j-range covers).  The lattice is cut into tiles of
+// T1 x T2 rows of axes 1 and 2, and each tile is swept through the whole of
+// axis 3 before the next, so that the neighbours along axes 2 and 3 of what a
+// pass is updating were read a short time before.  T1 = L1, T2 = L2 is plain
+// row order.  With half = 1 the row index counts axis-1 pairs (x1 = 2 y + p):
+// the caller passes y back in c[1].
+__device__ __forceinline__ void tile_rows(const Geo& g, uint32_t r, int c[4], int half) {
+  const uint32_t L1 = (uint32_t)(g.L[1] >> half), T1 = (uint32_t)(g.T1 >> half);
+  const uint32_t T2 = (uint32_t)g.T2, L3 = (uint32_t)g.L[3];
+  const uint32_t inner = T1 * T2 * L3;
+  const uint32_t tile = r / inner;
+  uint32_t q = r - tile * inner;
+  const uint32_t a = q % T1;
+  q /= T1;
+  const uint32_t b = q % T2;
+  const uint32_t x3 = q / T2;
+  const uint32_t n1 = L1 / T1;
+  const uint32_t t2 = tile / n1;
+  const uint32_t t1 = tile - t2 * n1;
+  c[1] = (int)(t1 * T1 + a);
+  c[2] = (int)(t2 * T2 + b);
+  c[3] = (int)x3;
+}
 
 __device__ __forceinline__ uint32_t site_index(const Geo& g, const int c[4]) {
   const uint32_t s = (uint32_t)(c[0] + c[1] + c[2] + c[3]) & 3u;
@@ -376,6 +402,38 @@ __device__ __forceinline__ M3<R> ld_link(const DirBuf<R>& b, uint32_t idx) {
   for (int e = 0; e < 6; ++e) ld_entry(b, voff, e, m.a[e]);
   rebuild_row2(m);
   return m;
+}
+
+// Rows 0 and 1 of a stored link as they are in memory (row 2 left zero and
+// never read): a link held across several uses costs two thirds of the
+// registers; full() rebuilds row 2 where a product needs it.
+template <typename R>
+__device__ __forceinline__ M3<R> ld_rows(const DirBuf<R>& b, uint32_t idx) {
+  M3<R> m;
+  const uint32_t voff = idx * (uint32_t)sizeof(typename R2<R>::type);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) ld_entry(b, voff, e, m.a[e]);
+#pragma unroll
+  for (int e = 6; e < 9; ++e) m.a[e] = cx<R>(R(0), R(0));
+  return m;
+}
+
+// Keeps the compiler from treating two rebuilds of the same rows as one value
+// (which would hold the rebuilt row live between the uses).
+__device__ __forceinline__ void opaque(double& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void opaque(float& v) { asm volatile("" : "+v"(v)); }
+
+template <typename R>
+__device__ __forceinline__ M3<R> full(const M3<R>& m) {
+  M3<R> f;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    f.a[e] = m.a[e];
+    opaque(f.a[e].re);
+    opaque(f.a[e].im);
+  }
+  rebuild_row2(f);
+  return f;
 }
 
 template <typename R>

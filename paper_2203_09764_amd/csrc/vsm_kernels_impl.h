@@ -253,26 +253,28 @@ __device__ __forceinline__ void staple_dir(M3<R>& S, const DirBuf<R>& bm, const 
 }
 
 // The same paths with every distinct link loaded once per orientation (10
-// loads instead of 14) and the plaquette staple sharing A B with the 2x1 path
+// loads instead of 18) and the plaquette staple sharing A B with the 2x1 path
 // whose site x sits at the left; K = U_mu(x+mu) and L = U_mu(x-mu) are common to
-// all nu and loaded once by the caller.  Needs about 5 live matrices besides
-// Sigma, K and L: used where matrices are FP32.
+// all nu and loaded once by the caller.  Links used more than once are held as
+// rows 0 and 1 and completed per use, which keeps the FP64 form within 256
+// VGPRs.
 template <typename R, bool UP>
 __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm, const DirBuf<R>& bn,
                                                   const Geo& g, const Nb& o, R cp, R cr,
                                                   const M3<R>& K, const M3<R>& L) {
   auto I = [&](int a, int b) { return nbi(g, o, a, b); };
   const int sg = UP ? 1 : -1;
-  const M3<R> Ar = ld_link(bn, I(0, UP ? 0 : -1));
+  // A, B, C are used several times: held as rows 0 and 1, completed per use
+  const M3<R> Ar = ld_rows(bn, I(0, UP ? 0 : -1));
   load_fence();
-  const M3<R> Cr = ld_link(bn, I(1, UP ? 0 : -1));
+  const M3<R> Cr = ld_rows(bn, I(1, UP ? 0 : -1));
   load_fence();
   // 1x2: A D E F^dag C^dag
   M3<R> w;
   {
     const M3<R> Dr = ld_link(bn, I(0, UP ? 1 : -2));
     load_fence();
-    w = UP ? mul2_nn(Ar, Dr) : mul2_dd(Ar, Dr);
+    w = UP ? mul2_nn(Ar, Dr) : mul2_dd(full(Ar), Dr);
   }
   chain_step<R, false>(w, bm, I(0, 2 * sg));
   {
@@ -280,29 +282,29 @@ __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm,
     load_fence();
     w = UP ? mul2_nd(w, Fr) : mul2_nn(w, Fr);
   }
-  w = UP ? mul2_nd(w, Cr) : mul2_nn(w, Cr);
+  w = UP ? mul2_nd(w, full(Cr)) : mul2_nn(w, full(Cr));
   chain_add(S, cr, w);
   // plaquette A B C^dag and 2x1 left A B G H^dag K^dag share T = A B
-  const M3<R> Br = ld_link(bm, I(0, sg));
+  const M3<R> Br = ld_rows(bm, I(0, sg));
   load_fence();
-  M3<R> T = UP ? mul2_nn(Ar, Br) : mul2_dn(Ar, Br);
-  chain_add(S, cp, UP ? mul2_nd(T, Cr) : mul2_nn(T, Cr));
+  M3<R> T = UP ? mul2_nn(Ar, full(Br)) : mul2_dn(full(Ar), full(Br));
+  chain_add(S, cp, UP ? mul2_nd(T, full(Cr)) : mul2_nn(T, full(Cr)));
   chain_step<R, false>(T, bm, I(1, sg));
   {
     const M3<R> Hr = ld_link(bn, I(2, UP ? 0 : -1));
     load_fence();
     T = UP ? mul2_nd(T, Hr) : mul2_nn(T, Hr);
   }
-  chain_add(S, cr, mul2_nd(T, K));
+  chain_add(S, cr, mul2_nd(T, full(K)));
   // 2x1 middle: L^dag M N B C^dag
   {
     const M3<R> Mr = ld_link(bn, I(-1, UP ? 0 : -1));
     load_fence();
-    w = UP ? mul2_dn(L, Mr) : mul2_dd(L, Mr);
+    w = UP ? mul2_dn(full(L), Mr) : mul2_dd(full(L), Mr);
   }
   chain_step<R, false>(w, bm, I(-1, sg));
-  w = mul2_nn(w, Br);
-  w = UP ? mul2_nd(w, Cr) : mul2_nn(w, Cr);
+  w = mul2_nn(w, full(Br));
+  w = UP ? mul2_nd(w, full(Cr)) : mul2_nn(w, full(Cr));
   chain_add(S, cr, w);
 }
 
@@ -448,11 +450,7 @@ template <int MU>
 __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t, int c[4]) {
   if (MU != 0) {
     const uint32_t xi = t % (uint32_t)g.Xq;
-    uint32_t r = t / (uint32_t)g.Xq;
-    c[1] = (int)(r % (uint32_t)g.L[1]);
-    r /= (uint32_t)g.L[1];
-    c[2] = (int)(r % (uint32_t)g.L[2]);
-    c[3] = (int)(r / (uint32_t)g.L[2]);
+    tile_rows(g, t / (uint32_t)g.Xq, c, 0);
     const int s = (colour - c[MU]) & 3;
     c[0] = (int)(4 * xi) + ((s - c[1] - c[2] - c[3]) & 3);
   } else {
@@ -461,12 +459,8 @@ __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t
     const uint32_t rem = t - k * two;
     const uint32_t which = rem / (uint32_t)g.Xq;
     const uint32_t xi = rem - which * (uint32_t)g.Xq;
-    const uint32_t half = (uint32_t)g.L[1] / 2u;
-    const uint32_t yh = k % half;
-    const uint32_t zt = k / half;
-    c[2] = (int)(zt % (uint32_t)g.L[2]);
-    c[3] = (int)(zt / (uint32_t)g.L[2]);
-    c[1] = (int)(2 * yh) + ((colour - c[2] - c[3]) & 1);
+    tile_rows(g, k, c, 1);
+    c[1] = 2 * c[1] + ((colour - c[2] - c[3]) & 1);
     const int S = c[1] + c[2] + c[3];
     const int h = ((colour - S) & 3) >> 1;
     c[0] = (int)(4 * xi) + h + 2 * (int)which;
@@ -505,15 +499,13 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
     o.dm[2] = jdelta(g, MU, c[MU], 1);
     o.dm[3] = jdelta(g, MU, c[MU], 2);
     M3<R> S = mzero<R>();
-#ifndef VSM_SHARED_STAPLE
-#define VSM_SHARED_STAPLE 1
-#endif
-    constexpr bool kShared = VSM_SHARED_STAPLE && OI && sizeof(R) == 4;
+    // over-improved staples: the factored form with U_mu(x +- mu) loaded once
+    constexpr bool kShared = OI;
     M3<R> K, Lm;
     if (kShared) {
-      K = ld_link(bm, nbi(g, o, 1, 0));
+      K = ld_rows(bm, nbi(g, o, 1, 0));
       load_fence();
-      Lm = ld_link(bm, nbi(g, o, -1, 0));
+      Lm = ld_rows(bm, nbi(g, o, -1, 0));
       load_fence();
     }
 #pragma unroll 1
@@ -888,10 +880,11 @@ void launch_update_mu(const Geo& g, const void* src, void* dst, const int8_t* z3
   const uint32_t n = jacobi ? g.V : g.V4;
   const unsigned nb = blocks_for(n, 256);
   const double2* gp = (const double2*)gauge;
-#ifndef VSM_LDS_PAD
-#define VSM_LDS_PAD 0
-#endif
-  const unsigned lds = VSM_LDS_PAD;
+  // Occupancy: the pass is bound by refetches of links that other waves read
+  // too; fewer resident blocks per CU keep more of that reuse in L2.  Unused
+  // dynamic LDS caps the blocks per CU (160 KB of LDS): 1 for FP64 (4 waves),
+  // 2 for FP32 (8 waves), the best measured on the 48^3x96 pass.
+  const unsigned lds = p.oi ? (sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u) : 0u;
   if (p.oi) {
     if (p.update == 0)
       hipLaunchKernelGGL((k_update<R, MU, true, 0>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
