@@ -126,7 +126,7 @@ def run_gpu_form(args, precision, dims, n, pairs):
     )
 
 
-def serving_leg(n_jobs: int, rate: float, seed: int = 3):
+def serving_leg(n_jobs: int, rate: float, slots: int = 64, seed: int = 3):
     """The serving stream: Poisson arrivals at `rate` jobs/s of smoothing jobs on
     8^4, 12^3x24, 16^3x32 and 20^3x40 vortex fields (p uniform in [0.05, 0.15],
     50-300 sweeps), FP32-bulk annealed over-improved stout with vortex
@@ -141,7 +141,7 @@ def serving_leg(n_jobs: int, rate: float, seed: int = 3):
         n = fieldgen.z3_vortex_charges(sp.dims, sp.p, sp.field_seed)
         pairs = fieldgen.centrifuge_pairs(sp.dims, sp.pair_seed)
         jobs.append((sp.arrival_s, sp.dims, n, pairs, sp.n_sweeps))
-    with serve.Server(hbm_budget_bytes=16 << 30, host_budget_bytes=256 << 20, max_slots=64,
+    with serve.Server(hbm_budget_bytes=16 << 30, host_budget_bytes=256 << 20, max_slots=slots,
                       max_inflight=4) as srv:
         r = serve.run_stream(srv, jobs, precision="fp32_bulk", measure_every=0, rho=0.06, eps=-0.25,
                              vp=True, omega=0.02, timeout=600)
@@ -190,6 +190,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=200, help="jobs of the serving stream (0: skip)")
     ap.add_argument("--serving-rate", type=float, default=50.0, help="mean arrivals per second")
+    ap.add_argument("--serving-slots", type=int, default=64, help="jobs resident at once")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -254,7 +255,7 @@ def main():
         forms_out["fp32_bulk"]["max_rel_action_dev_vs_fp64"] = max(abs(x - y) / abs(y) for x, y in zip(a32, a64))
     out["forms"] = forms_out
     if args.serving_jobs > 0:
-        out["serving"] = serving_leg(args.serving_jobs, args.serving_rate)
+        out["serving"] = serving_leg(args.serving_jobs, args.serving_rate, args.serving_slots)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(dims, n, pairs, args.cpu_threads)
     print(json.dumps(out), flush=True)

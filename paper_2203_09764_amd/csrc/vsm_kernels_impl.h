@@ -916,7 +916,9 @@ void launch_update_t(const Geo& g, const void* src, void* dst, const int8_t* z3,
 
 template <typename R>
 void launch_update_batch_t(const ServeJob* jobs, const BatchStep& step, uint32_t nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_batch<R>, dim3(nblocks), dim3(256), 0, st, jobs, step);
+  // the same cap on resident blocks per CU as for single-field passes
+  const unsigned lds = sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u;
+  hipLaunchKernelGGL(k_update_batch<R>, dim3(nblocks), dim3(256), lds, st, jobs, step);
 }
 
 template <typename R>

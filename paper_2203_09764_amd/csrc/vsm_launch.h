@@ -41,7 +41,7 @@ struct ServeJob {
 // job, all in one launch.  Job i owns blocks [first_block[i], first_block[i+1])
 // (the last one up to the grid size) and runs subset `colour[i]` of internal
 // direction mu[i] on jobs[slot[i]].
-constexpr int kBatchMax = 16;
+constexpr int kBatchMax = 64;
 struct BatchStep {
   uint32_t first_block[kBatchMax];
   uint32_t slot[kBatchMax];

@@ -102,19 +102,21 @@ def test_staggered_arrivals_are_bit_identical(server, alone):
         assert _same(alone[len(JOBS) - 1 - k], got[ids[k]]), f"job {j} differs when staggered"
 
 
-def test_more_jobs_than_one_launch_holds(server):
-    """Twenty resident jobs: steps span two launches (at most 16 jobs each)."""
+def test_more_jobs_than_one_launch_holds():
+    """Seventy resident jobs: a step then spans two launches (at most 64 jobs each)."""
     dims, prec, ns, seed = (8, 8, 8, 8), "fp32_bulk", 40, 21
     n, pairs = _inputs(dims, seed)
     kw = dict(pairs=pairs, n_sweeps=ns, precision=prec, measure_every=4, want_links=True, **KW)
-    ref_id = server.submit(dims, n, **kw)
-    assert server.wait(ref_id, 120)["state"] == "done"
-    ref = server.fetch(ref_id)
-    ids = [server.submit(dims, n, **kw) for _ in range(20)]
-    for jid in ids:
-        assert server.wait(jid, 120)["state"] == "done"
-        assert _same(ref, server.fetch(jid))
-    assert server.counters()["peak_resident_jobs"] >= 17
+    with serve.Server(hbm_budget_bytes=1 << 30, host_budget_bytes=256 << 20, max_slots=80) as srv:
+        ref_id = srv.submit(dims, n, **kw)
+        assert srv.wait(ref_id, 120)["state"] == "done"
+        ref = srv.fetch(ref_id)
+        ids = [srv.submit(dims, n, **kw) for _ in range(70)]
+        for jid in ids:
+            assert srv.wait(jid, 120)["state"] == "done"
+            assert _same(ref, srv.fetch(jid))
+        c = srv.counters()
+    assert c["peak_resident_jobs"] > 64
 
 
 def test_served_equals_single_field_path(alone):
