@@ -673,22 +673,25 @@ __device__ __forceinline__ int link_sector(const M3<double>& u) {
 template <typename R>
 __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const int8_t* __restrict__ z3,
                                                  Partial* __restrict__ part, int8_t* __restrict__ flux) {
-  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   KSum kp = {0.0, 0.0}, ka = {0.0, 0.0};
   double maxu = 0.0;
   long long mism = 0, undef = 0, nonfin = 0;
-  if (x < g.V) {
+  if (t < g.V) {
     int c[4];
-    coords_of_index(g, x, c);
+    coords_of_index(g, t, c);
+    const uint32_t x = site_index(g, c);
     const uint32_t s = canonical_index(g, c);
-    // sectors and original charges of the four links at x (user directions), one byte each
+    // original charges of the four links at x (user directions), one byte each;
+    // their sectors are filled in as the links are first read
     uint32_t secb = 0, n0b = 0;
-#pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-      const M3<double> U = mconvert<double>(ld_link(dir_buf<R>(links, g, g.perm[mu]), x));
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) n0b |= (uint32_t)(z3[(size_t)mu * g.V + s] & 0xff) << (8 * mu);
+    auto byte_at = [](uint32_t w, int i) { return (int)(int8_t)((w >> (8 * i)) & 0xffu); };
+    // sector, finiteness and unitarity of an own link, once per link
+    auto own_checks = [&](const M3<double>& U, int mu) {
       const int sc = link_sector(U);
       secb |= (uint32_t)(sc & 0xff) << (8 * mu);
-      n0b |= (uint32_t)(z3[(size_t)mu * g.V + s] & 0xff) << (8 * mu);
       bool fin = true;
 #pragma unroll
       for (int e = 0; e < 9; ++e) fin = fin && isfinite(U.a[e].re) && isfinite(U.a[e].im);
@@ -701,49 +704,59 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
         const double dv = sqrt(dr * dr + uu.a[e].im * uu.a[e].im);
         maxu = fmax(maxu, dv);
       }
-    }
-    auto byte_at = [](uint32_t w, int i) { return (int)(int8_t)((w >> (8 * i)) & 0xffu); };
+    };
+    // planes 01, 02, 03, 12, 13, 23 (user axes), mu outer so that A = U_mu(x)
+    // is read once per mu; D = U_nu(x) is read per plane (from cache after
+    // its first read)
 #pragma unroll 1
-    for (int plane = 0; plane < 6; ++plane) {
-      // user planes 01, 02, 03, 12, 13, 23
-      const int mu = plane < 3 ? 0 : (plane < 5 ? 1 : 2);
-      const int nu = plane < 3 ? plane + 1 : (plane < 5 ? plane - 1 : 3);
-      const int dm = g.perm[mu], dn = g.perm[nu];
-      int cm[4] = {c[0], c[1], c[2], c[3]};
-      cm[dm] = wrap_add(cm[dm], 1, g.L[dm]);
-      int cn[4] = {c[0], c[1], c[2], c[3]};
-      cn[dn] = wrap_add(cn[dn], 1, g.L[dn]);
-      const DirBuf<R> bmu = dir_buf<R>(links, g, dm), bnu = dir_buf<R>(links, g, dn);
+    for (int mu = 0; mu < 3; ++mu) {
+      const int dm = g.perm[mu];
+      const DirBuf<R> bmu = dir_buf<R>(links, g, dm);
       const M3<double> A = mconvert<double>(ld_link(bmu, x));
       load_fence();
-      const M3<double> B = mconvert<double>(ld_link(bnu, site_index(g, cm)));
-      load_fence();
-      const int sb = link_sector(B);
-      M3<double> P = mul_nn(A, B);
-      const M3<double> Cm = mconvert<double>(ld_link(bmu, site_index(g, cn)));
-      load_fence();
-      const int sc = link_sector(Cm);
-      P = mul_nd(P, Cm);
-      P = mul_nd(P, mconvert<double>(ld_link(bnu, x)));
-      load_fence();
-      const double rt = P.a[0].re + P.a[4].re + P.a[8].re;
-      const double ra = (1.0 - P.a[0].re) + (1.0 - P.a[4].re) + (1.0 - P.a[8].re);
-      kadd(kp, rt);
-      kadd(ka, ra);
-      const int smu = byte_at(secb, mu), snu = byte_at(secb, nu);
-      const int o = byte_at(n0b, mu) + (int)z3[(size_t)nu * g.V + canonical_index(g, cm)] -
-                    (int)z3[(size_t)mu * g.V + canonical_index(g, cn)] - byte_at(n0b, nu);
-      const int orig = ((o % 3) + 3) % 3;
-      int pv;
-      if (smu == kUndef || sb == kUndef || sc == kUndef || snu == kUndef) {
-        ++mism;
-        pv = kUndef;
-      } else {
-        const int r = (((smu + sb - sc - snu) % 3) + 3) % 3;
-        if (r != orig) ++mism;
-        pv = (r == 2) ? -1 : r;
+      if (mu == 0) own_checks(A, 0);
+      int cn[4];
+#pragma unroll 1
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        const int plane = mu == 0 ? nu - 1 : (mu == 1 ? nu + 1 : 5);
+        const int dn = g.perm[nu];
+        const DirBuf<R> bnu = dir_buf<R>(links, g, dn);
+        int cm[4] = {c[0], c[1], c[2], c[3]};
+        cm[dm] = wrap_add(cm[dm], 1, g.L[dm]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cn[k] = c[k];
+        cn[dn] = wrap_add(cn[dn], 1, g.L[dn]);
+        const M3<double> B = mconvert<double>(ld_link(bnu, site_index(g, cm)));
+        load_fence();
+        const int sb = link_sector(B);
+        M3<double> P = mul_nn(A, B);
+        const M3<double> Cm = mconvert<double>(ld_link(bmu, site_index(g, cn)));
+        load_fence();
+        const int sc = link_sector(Cm);
+        P = mul_nd(P, Cm);
+        const M3<double> D = mconvert<double>(ld_link(bnu, x));
+        load_fence();
+        if (mu == 0) own_checks(D, nu);
+        P = mul_nd(P, D);
+        const double rt = P.a[0].re + P.a[4].re + P.a[8].re;
+        const double ra = (1.0 - P.a[0].re) + (1.0 - P.a[4].re) + (1.0 - P.a[8].re);
+        kadd(kp, rt);
+        kadd(ka, ra);
+        const int smu = byte_at(secb, mu), snu = byte_at(secb, nu);
+        const int o = byte_at(n0b, mu) + (int)z3[(size_t)nu * g.V + canonical_index(g, cm)] -
+                      (int)z3[(size_t)mu * g.V + canonical_index(g, cn)] - byte_at(n0b, nu);
+        const int orig = ((o % 3) + 3) % 3;
+        int pv;
+        if (smu == kUndef || sb == kUndef || sc == kUndef || snu == kUndef) {
+          ++mism;
+          pv = kUndef;
+        } else {
+          const int r = (((smu + sb - sc - snu) % 3) + 3) % 3;
+          if (r != orig) ++mism;
+          pv = (r == 2) ? -1 : r;
+        }
+        if (flux) flux[(size_t)plane * g.V + s] = (int8_t)pv;
       }
-      if (flux) flux[(size_t)plane * g.V + s] = (int8_t)pv;
     }
   }
   // wave reduction (fixed butterfly), then a fixed-order pass over the 4 waves
