@@ -98,8 +98,9 @@ int vsm_check_dims(const int32_t dims[4], int32_t order, int32_t precision);
 /* Bytes of the internal link buffer (0 for invalid arguments). */
 size_t vsm_links_bytes(const int32_t dims[4], int32_t precision);
 /* Bytes of device workspace that vsm_smooth / vsm_measure / vsm_pass need for
- * this order: reduction slots and counters, plus a second link buffer for
- * VSM_JACOBI.  0 for invalid arguments. */
+ * this order: counters, reduction slots and a copy of the charges in the
+ * internal layout (4V bytes), plus a second link buffer for VSM_JACOBI.  0 for
+ * invalid arguments. */
 size_t vsm_workspace_bytes(const int32_t dims[4], int32_t precision, int32_t order);
 
 /* Copy links in from / out to the canonical interchange layout:

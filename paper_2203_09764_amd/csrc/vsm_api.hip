@@ -129,6 +129,12 @@ int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const 
   char* ws = (char*)workspace_dev;
   unsigned long long* rej = (unsigned long long*)(ws + w.counters);
   VsmStatsDev* out = (VsmStatsDev*)stats_dev;
+  // the measurement reads the charges in the internal layout
+  int8_t* z3i = nullptr;
+  if (measure_every > 0) {
+    z3i = (int8_t*)(ws + w.charges);
+    launch_charges(g, z3_dev, z3i, 0, 4, st);
+  }
   launch_zero_u64(rej, 1, st);
   void* cur = links_dev;
   void* other = ws + w.field;
@@ -143,11 +149,11 @@ int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const 
     } else {
       for (int mu = 0; mu < 4; ++mu)
         for (int c = 0; c < 4; ++c)
-          launch_update(precision, g, links_dev, links_dev, z3_dev, gauge_dev, p, g.perm[mu], kColours[c],
-                        0, rej, st);
+          launch_update(precision, g, links_dev, links_dev, z3_dev, gauge_dev, p, g.perm[mu], kColours[c], 0,
+                        rej, st);
     }
     if (measure_every > 0 && (sw + 1) % measure_every == 0) {
-      launch_measure(precision, g, cur, z3_dev, ws + w.partials, nullptr, rej, out + rec, sw + 1, st);
+      launch_measure(precision, g, cur, z3i, ws + w.partials, nullptr, rej, out + rec, sw + 1, st);
       ++rec;
     }
   }
@@ -188,9 +194,11 @@ int vsm_measure(const int32_t dims[4], int32_t precision, const void* links_dev,
   const WsLayout w = ws_layout(dims, precision, VSM_ANNEALED);
   if (workspace_bytes < w.total) return VSM_E_WORKSPACE;
   char* ws = (char*)workspace_dev;
-  launch_measure(precision, make_geo(dims), links_dev, z3_dev, ws + w.partials, flux_dev,
-                 (unsigned long long*)(ws + w.counters), (VsmStatsDev*)stats_dev, -1,
-                 (hipStream_t)stream);
+  const Geo g = make_geo(dims);
+  hipStream_t st = (hipStream_t)stream;
+  launch_charges(g, z3_dev, (int8_t*)(ws + w.charges), 0, 4, st);
+  launch_measure(precision, g, links_dev, (const int8_t*)(ws + w.charges), ws + w.partials, flux_dev,
+                 (unsigned long long*)(ws + w.counters), (VsmStatsDev*)stats_dev, -1, st);
   return hip_status();
 }
 

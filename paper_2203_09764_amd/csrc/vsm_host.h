@@ -91,10 +91,11 @@ inline Geo make_geo(const int32_t dims[4]) {
   return g;
 }
 
-// Workspace: [0, 256) counters (rejections at 0); then the measurement block
-// partials; then, for the smearing schedule, a second link buffer.
+// Workspace: [0, 256) counters (rejections at 0); the measurement block
+// partials; the original charges in the internal layout (4V bytes); then, for
+// the smearing schedule, a second link buffer.
 struct WsLayout {
-  size_t counters, partials, field, total;
+  size_t counters, partials, charges, field, total;
 };
 
 inline WsLayout ws_layout(const int32_t dims[4], int32_t precision, int32_t order) {
@@ -102,7 +103,8 @@ inline WsLayout ws_layout(const int32_t dims[4], int32_t precision, int32_t orde
   WsLayout w;
   w.counters = 0;
   w.partials = 256;
-  w.field = align256(w.partials + (size_t)measure_blocks(g) * partial_bytes());
+  w.charges = align256(w.partials + (size_t)measure_blocks(g) * partial_bytes());
+  w.field = align256(w.charges + 4ull * g.V);
   w.total = w.field;
   if (order == VSM_JACOBI) w.total += align256(24ull * g.V * entry_bytes(precision));
   return w;

@@ -30,6 +30,26 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
+// Charges from the canonical layout (user direction, canonical site) to the
+// internal one (internal direction d, internal site index) for directions
+// d0 .. d0 + nd - 1, so that the update and measurement kernels read them with
+// the same coalesced index as the links.
+__global__ void k_charges(Geo g, const int8_t* __restrict__ z3, int8_t* __restrict__ out, int d0,
+                          int nd) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (size_t)nd * g.V) return;
+  const int d = d0 + (int)(tid / g.V);
+  const uint32_t idx = (uint32_t)(tid % g.V);
+  int c[4];
+  coords_of_index(g, idx, c);
+  out[(size_t)d * g.V + idx] = z3[(size_t)g.uperm[d] * g.V + canonical_index(g, c)];
+}
+
+void launch_charges(const Geo& g, const int8_t* z3, int8_t* out, int d0, int nd, hipStream_t st) {
+  const size_t n = (size_t)nd * g.V;
+  hipLaunchKernelGGL(k_charges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, z3, out, d0, nd);
+}
+
 void launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, p, n);
 }

@@ -471,7 +471,8 @@ __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t
 // annealing subset `colour`, in place (src == dst); jacobi = 1, link t of
 // direction MU from src into dst (smearing).  UPD = 0 stout, 1 MaxReTr.  With
 // vp, a candidate is kept only if its centre sector (after undoing the gauge
-// transform, when one is given) equals the original charge.  Returns whether a
+// transform, when one is given) equals the original charge (z3, canonical
+// layout: one byte per update, not worth a relayout).  Returns whether a
 // candidate was rejected.
 template <typename R, int MU, bool OI, int UPD>
 __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* dst,
@@ -667,8 +668,9 @@ __device__ __forceinline__ int link_sector(const M3<double>& u) {
 // Re Tr P and Re Tr[1 - P] (Sec. V.A); the sectors of the four links at x;
 // the vortex flux of every plaquette from the link sectors compared with the
 // flux of the original charges; unitarity and finiteness of the own links.
-// Threads run over the internal site index; planes and charges use user axes.
-// Block partials go to fixed slots; k_finalize sums them in a fixed order, so
+// Threads run over the internal site index; planes use user axes; the
+// original charges z3 are in the internal layout (k_charges).  Block partials
+// go to fixed slots; k_finalize sums them in a fixed order, so
 // the result does not depend on the scheduling.
 template <typename R>
 __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const int8_t* __restrict__ z3,
@@ -686,7 +688,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
     // their sectors are filled in as the links are first read
     uint32_t secb = 0, n0b = 0;
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) n0b |= (uint32_t)(z3[(size_t)mu * g.V + s] & 0xff) << (8 * mu);
+    for (int mu = 0; mu < 4; ++mu) n0b |= (uint32_t)(z3[(size_t)g.perm[mu] * g.V + x] & 0xff) << (8 * mu);
     auto byte_at = [](uint32_t w, int i) { return (int)(int8_t)((w >> (8 * i)) & 0xffu); };
     // sector, finiteness and unitarity of an own link, once per link
     auto own_checks = [&](const M3<double>& U, int mu) {
@@ -743,8 +745,8 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
         kadd(kp, rt);
         kadd(ka, ra);
         const int smu = byte_at(secb, mu), snu = byte_at(secb, nu);
-        const int o = byte_at(n0b, mu) + (int)z3[(size_t)nu * g.V + canonical_index(g, cm)] -
-                      (int)z3[(size_t)mu * g.V + canonical_index(g, cn)] - byte_at(n0b, nu);
+        const int o = byte_at(n0b, mu) + (int)z3[(size_t)dn * g.V + site_index(g, cm)] -
+                      (int)z3[(size_t)dm * g.V + site_index(g, cn)] - byte_at(n0b, nu);
         const int orig = ((o % 3) + 3) % 3;
         int pv;
         if (smu == kUndef || sb == kUndef || sc == kUndef || snu == kUndef) {

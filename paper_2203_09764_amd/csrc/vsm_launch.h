@@ -32,7 +32,7 @@ struct VsmStatsDev {
 struct ServeJob {
   Geo g;
   void* links;
-  const int8_t* z3;
+  const int8_t* z3;  // original charges, canonical layout
   unsigned long long* rej;  // the job's rejection counter
   UpdParams p;
 };
@@ -69,6 +69,9 @@ inline uint32_t pass_blocks(const Geo& g) { return (g.V4 + 255u) / 256u; }
 // One serving step: every job of `step` (stout updates, annealed, in place).
 void launch_update_batch(int prec, const ServeJob* jobs_dev, const BatchStep& step, uint32_t nblocks,
                          hipStream_t st);
+// Charges z3 (canonical layout) into out (internal layout, 4V bytes) for the
+// internal directions d0 .. d0 + nd - 1.
+void launch_charges(const Geo& g, const int8_t* z3, int8_t* out, int d0, int nd, hipStream_t st);
 void launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 
 }  // namespace vsm

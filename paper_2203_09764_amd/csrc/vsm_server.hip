@@ -192,9 +192,9 @@ class Server {
 
   int enqueue_measure(Job* j, long long sweep) {
     char* d = j->dbase;
-    launch_measure(j->desc.precision, j->g, d + j->lay.links, (const int8_t*)(d + j->lay.z3),
-                   d + j->lay.ws + ws_layout(j->desc.dims, j->desc.precision, VSM_ANNEALED).partials,
-                   nullptr, (unsigned long long*)(d + j->lay.ws),
+    const WsLayout w = ws_layout(j->desc.dims, j->desc.precision, VSM_ANNEALED);
+    launch_measure(j->desc.precision, j->g, d + j->lay.links, (const int8_t*)(d + j->lay.ws + w.charges),
+                   d + j->lay.ws + w.partials, nullptr, (unsigned long long*)(d + j->lay.ws),
                    (VsmStatsDev*)(d + j->lay.records) + j->rec, sweep, stream);
     ++j->rec;
     ++ctr.launches;
@@ -274,8 +274,11 @@ class Server {
                           (const int8_t*)(d + j->lay.pairs), j->desc.omega, d + j->lay.links, nullptr, stream);
       else
         launch_load_z3(j->desc.precision, j->g, (const int8_t*)(d + j->lay.z3), d + j->lay.links, stream);
+      launch_charges(j->g, (const int8_t*)(d + j->lay.z3),
+                     (int8_t*)(d + j->lay.ws + ws_layout(j->desc.dims, j->desc.precision, VSM_ANNEALED).charges), 0,
+                     4, stream);
       launch_zero_u64((unsigned long long*)(d + j->lay.ws), 1, stream);
-      ctr.launches += 2;
+      ctr.launches += 3;
       int rc = hip_status();
       if (rc) return rc;
       const int64_t resident = (int64_t)(running.size() + finishing.size());
