@@ -259,3 +259,35 @@ def test_api_errors_do_not_launch():
     with pytest.raises(api._lib.VsmError):
         api.Field((8, 8, 6, 8)).dims and api.smooth(api.Field((8, 8, 6, 8)), 1, 0.1, 1.0,
                                                      order="annealed")
+
+
+@pytest.mark.parametrize("dims,alpha", [((16, 16, 16, 32), 0.7), ((16, 16, 16, 32), 0.02),
+                                        ((32, 32, 32, 64), 0.7)])
+def test_vp_maxretr_leaves_a_z3_field_unchanged(dims, alpha):
+    """Sec. VI, first sweep on an unconditioned Z(3) field: every MaxReTr update
+    that moves a vortex link (|phi| > pi/2) leaves its sector (p_pass = 0,
+    pinned on the CPU by the beta -> 0 enumeration), so vortex preservation
+    rejects all of them; the other links get updates that are the identity up to
+    the rounding of the staple sums.  So the field after an annealed
+    over-improved sweep is the original to rounding, the rejection count equals
+    the oracle's, and there are none below alpha_min."""
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 41)
+    f = _field(dims)
+    f.set_charges(n)
+    api.load_z3(f, n)
+    before = _links(f)
+    st = _stats(api.smooth(f, 1, 0.0, -0.25, order="annealed", update="maxretr", alpha=alpha, vp=True,
+                           measure_every=1), 1)
+    after = _links(f)
+    assert np.abs(after - before).max() < 1e-10
+    U = ora.z3_field(dims, n)
+    so = ora.smooth(dims, U, n, 1, order="annealed", update="maxretr", alpha=alpha, eps=-0.25, vp=True)
+    assert int(st.rejected[0]) == int(so.rejected[0])
+    # where the staple sum nearly cancels v (|L^1| small) the SU(2) hit divides
+    # by a small k, which scales rounding differences up: 1e-10 here
+    assert np.abs(after - U).max() < 1e-10
+    if alpha < 0.4486:
+        assert int(st.rejected[0]) == 0
+    else:
+        assert int(st.rejected[0]) > 0
+    assert int(st.flux_mismatch[0]) == 0
