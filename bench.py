@@ -126,6 +126,42 @@ def run_gpu_form(args, precision, dims, n, pairs):
     )
 
 
+def maxretr_form(dims, n, pairs, precision, sweeps=2, alpha=0.7):
+    """The MaxReTr update (annealed, over-improved eps = -0.25, alpha = 0.7, three
+    SU(2) loops, vortex preservation) on the same preconditioned field: its
+    subset passes timed with events, as for the stout pass."""
+    import torch
+
+    from paper_2203_09764_amd import api
+
+    f = api.Field(dims, precision, device="cuda:0", jacobi_workspace=False)
+    f.set_charges(n)
+    api.precondition(f, pairs, 0.02)
+    kw = dict(update="maxretr", alpha=alpha, vp=True)
+    for mu in range(4):  # one untimed sweep
+        for colour in (0, 2, 1, 3):
+            api.anneal_pass(f, mu, colour, 0.0, -0.25, **kw)
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(16 * sweeps + 1)]
+    k = 0
+    evs[0].record(stream)
+    for _ in range(sweeps):
+        for mu in range(4):
+            for colour in (0, 2, 1, 3):
+                api.anneal_pass(f, mu, colour, 0.0, -0.25, **kw)
+                k += 1
+                evs[k].record(stream)
+    torch.cuda.synchronize()
+    durs = [evs[i].elapsed_time(evs[i + 1]) for i in range(16 * sweeps)]
+    avg = sum(durs) / len(durs)
+    st = api.stats_to_numpy(api.measure(f), 1)[0]
+    lu = f.V // 4
+    return {"update": "MaxReTr alpha=%g, 3 SU(2) loops, eps=-0.25, vortex preservation" % alpha,
+            "avg_pass_ms": round(avg, 4), "lu_per_s": round(lu / (avg * 1e-3), 1),
+            "hbm_frac": round(lu * pass_bytes_per_lu(precision) / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "flux_mismatch": int(st.flux_mismatch)}
+
+
 def serving_leg(n_jobs: int, rate: float, slots: int = 64, seed: int = 3):
     """The serving stream: Poisson arrivals at `rate` jobs/s of smoothing jobs on
     8^4, 12^3x24, 16^3x32 and 20^3x40 vortex fields (p uniform in [0.05, 0.15],
@@ -253,6 +289,8 @@ def main():
         a64, a32 = res["fp64"]["action"], res["fp32_bulk"]["action"]
         forms_out["fp32_bulk"]["speedup_vs_fp64"] = round(res["fp32_bulk"]["lu_per_s"] / res["fp64"]["lu_per_s"], 3)
         forms_out["fp32_bulk"]["max_rel_action_dev_vs_fp64"] = max(abs(x - y) / abs(y) for x, y in zip(a32, a64))
+    for p in forms:
+        forms_out[p + "_maxretr"] = maxretr_form(dims, n, pairs, p)
     out["forms"] = forms_out
     if args.serving_jobs > 0:
         out["serving"] = serving_leg(args.serving_jobs, args.serving_rate, args.serving_slots)
