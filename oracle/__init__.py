@@ -66,6 +66,8 @@ def lib():
                                                i32, i64, P, P]),
             "ora_update_links": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32,
                                                 i64, P, P, P, P]),
+            "ora_clover": (ctypes.c_int, [P, P, P, P, P]),
+            "ora_correlation": (ctypes.c_double, [i64, P, P]),
             "ora_pass": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32, i32,
                                         i32, P]),
             "ora_smooth": (ctypes.c_int, [P, P, P, P, i32, i32, i32, i32, f64, f64, f64, f64,
@@ -243,6 +245,26 @@ def measure(dims, links, n0, with_flux=False):
     _check(lib().ora_measure(_p(_dims(dims)), _p(links), _p(n0), _p(st), _p(flux)), "measure")
     rec = st.view(np.recarray)[0]
     return (rec, flux) if with_flux else rec
+
+
+def clover(dims, links, densities=False):
+    """(<S_R>/beta, Q, <S>/beta) from the 1x1 clover field strength; with
+    densities, also S(x)/beta and q(x) as float64 [V] (canonical order)."""
+    links = np.ascontiguousarray(links, dtype=np.complex128)
+    out = np.zeros(3, dtype=np.float64)
+    V = _vol(dims)
+    sd = np.empty(V, dtype=np.float64) if densities else None
+    qd = np.empty(V, dtype=np.float64) if densities else None
+    _check(lib().ora_clover(_p(_dims(dims)), _p(links), _p(out), _p(sd), _p(qd)), "clover")
+    sr, q, s = (float(v) for v in out)
+    return (sr, q, s, sd, qd) if densities else (sr, q, s)
+
+
+def correlation(a, b) -> float:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    assert a.shape == b.shape
+    return float(lib().ora_correlation(a.size, _p(a), _p(b)))
 
 
 def sectors(dims, links) -> np.ndarray:

@@ -814,6 +814,141 @@ static int measure(const lattice *g, const double *links, const int8_t *n0, ora_
   return ORA_OK;
 }
 
+/* The 1x1 clover term C_{mu nu}(x): the mean of the four plaquettes of the
+ * (mu, nu) plane that start and end at x, each taken in the mu -> nu sense. */
+static mat3 clover(const lattice *g, const double *links, int64_t x, int mu, int nu) {
+  const int64_t xpm = fwd(g, x, mu), xpn = fwd(g, x, nu);
+  const int64_t xmm = bwd(g, x, mu), xmn = bwd(g, x, nu);
+  const int64_t xmm_pn = fwd(g, xmm, nu), xmm_mn = bwd(g, xmm, nu), xpm_mn = fwd(g, xmn, mu);
+  mat3 leaf[4];
+  {
+    /* U_mu(x) U_nu(x+mu) U_mu^dag(x+nu) U_nu^dag(x) */
+    mat3 a = m_link(links, g, mu, x), b = m_link(links, g, nu, xpm);
+    mat3 c = m_link(links, g, mu, xpn), d = m_link(links, g, nu, x);
+    mat3 cd = m_dag(&c), dd = m_dag(&d), t = m_mul(&a, &b), t2 = m_mul(&t, &cd);
+    leaf[0] = m_mul(&t2, &dd);
+  }
+  {
+    /* U_nu(x) U_mu^dag(x-mu+nu) U_nu^dag(x-mu) U_mu(x-mu) */
+    mat3 a = m_link(links, g, nu, x), b = m_link(links, g, mu, xmm_pn);
+    mat3 c = m_link(links, g, nu, xmm), d = m_link(links, g, mu, xmm);
+    mat3 bd = m_dag(&b), cd = m_dag(&c), t = m_mul(&a, &bd), t2 = m_mul(&t, &cd);
+    leaf[1] = m_mul(&t2, &d);
+  }
+  {
+    /* U_mu^dag(x-mu) U_nu^dag(x-mu-nu) U_mu(x-mu-nu) U_nu(x-nu) */
+    mat3 a = m_link(links, g, mu, xmm), b = m_link(links, g, nu, xmm_mn);
+    mat3 c = m_link(links, g, mu, xmm_mn), d = m_link(links, g, nu, xmn);
+    mat3 ad = m_dag(&a), bd = m_dag(&b), t = m_mul(&ad, &bd), t2 = m_mul(&t, &c);
+    leaf[2] = m_mul(&t2, &d);
+  }
+  {
+    /* U_nu^dag(x-nu) U_mu(x-nu) U_nu(x+mu-nu) U_mu^dag(x) */
+    mat3 a = m_link(links, g, nu, xmn), b = m_link(links, g, mu, xmn);
+    mat3 c = m_link(links, g, nu, xpm_mn), d = m_link(links, g, mu, x);
+    mat3 ad = m_dag(&a), dd = m_dag(&d), t = m_mul(&ad, &b), t2 = m_mul(&t, &c);
+    leaf[3] = m_mul(&t2, &dd);
+  }
+  mat3 s01 = m_add(&leaf[0], &leaf[1]), s23 = m_add(&leaf[2], &leaf[3]), sum = m_add(&s01, &s23);
+  return m_scale(&sum, 0.25);
+}
+
+/* Sec. V, Eqs. (1LFST), (1LTopQ) and the reconstructed action of Sec. V.A, with
+ * g = 1:  F_{mu nu} = (C - C^dag)/(2i) (no trace removed, as written),
+ * q(x) = 1/(32 pi^2) eps_{mu nu rho sigma} Tr[F_{mu nu} F_{rho sigma}] summed
+ * over all 24 orderings, and S_R(x)/beta = 1/(2 n_c n_d (n_d - 1)) times the sum
+ * of Tr[F F] over the six planes (mu < nu: the reading under which S_R tends to
+ * S for smooth fields).  out = {<S_R>/beta, Q = sum_x q(x), <S>/beta}; sdens and
+ * qdens (may be NULL) receive S(x)/beta and q(x). */
+int ora_clover(const int32_t dims[4], const double *links, double *out, double *sdens, double *qdens) {
+  if (!links || !out) return ORA_E_NULL;
+  lattice g;
+  int rc = lat_init(&g, dims);
+  if (rc) return rc;
+  const int64_t V = g.V;
+  long double *sr = (long double *)malloc(sizeof(long double) * (size_t)V);
+  long double *qq = (long double *)malloc(sizeof(long double) * (size_t)V);
+  long double *ss = (long double *)malloc(sizeof(long double) * (size_t)V);
+  if (!sr || !qq || !ss) {
+    free(sr);
+    free(qq);
+    free(ss);
+    lat_free(&g);
+    return ORA_E_PARAM;
+  }
+  static const int perm4[24][4] = {
+      {0, 1, 2, 3}, {0, 1, 3, 2}, {0, 2, 1, 3}, {0, 2, 3, 1}, {0, 3, 1, 2}, {0, 3, 2, 1},
+      {1, 0, 2, 3}, {1, 0, 3, 2}, {1, 2, 0, 3}, {1, 2, 3, 0}, {1, 3, 0, 2}, {1, 3, 2, 0},
+      {2, 0, 1, 3}, {2, 0, 3, 1}, {2, 1, 0, 3}, {2, 1, 3, 0}, {2, 3, 0, 1}, {2, 3, 1, 0},
+      {3, 0, 1, 2}, {3, 0, 2, 1}, {3, 1, 0, 2}, {3, 1, 2, 0}, {3, 2, 0, 1}, {3, 2, 1, 0}};
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < V; ++x) {
+    mat3 F[4][4];
+    for (int mu = 0; mu < 4; ++mu) F[mu][mu] = m_zero();
+    long double s_r = 0.0L, s_w = 0.0L;
+    for (int mu = 0; mu < 4; ++mu)
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        mat3 C = clover(&g, links, x, mu, nu);
+        mat3 Cd = m_dag(&C);
+        mat3 diff = m_sub(&C, &Cd);
+        F[mu][nu] = m_scale(&diff, 1.0 / (2.0 * I));
+        mat3 neg = m_scale(&F[mu][nu], -1.0);
+        F[nu][mu] = neg;
+        mat3 ff = m_mul(&F[mu][nu], &F[mu][nu]);
+        s_r += (long double)creal(m_trace(&ff));
+        /* the plaquette at x, for S(x): both orders of the plane */
+        mat3 a = m_link(links, &g, mu, x), b = m_link(links, &g, nu, fwd(&g, x, mu));
+        mat3 c = m_link(links, &g, mu, fwd(&g, x, nu)), d = m_link(links, &g, nu, x);
+        mat3 cd = m_dag(&c), dd = m_dag(&d), t = m_mul(&a, &b), t2 = m_mul(&t, &cd);
+        mat3 P = m_mul(&t2, &dd);
+        s_w += 2.0L * (3.0L - (long double)creal(m_trace(&P)));
+      }
+    long double q = 0.0L;
+    for (int k = 0; k < 24; ++k) {
+      const int *pm = perm4[k];
+      /* sign of the permutation: count inversions */
+      int inv = 0;
+      for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j)
+          if (pm[i] > pm[j]) ++inv;
+      mat3 prod = m_mul(&F[pm[0]][pm[1]], &F[pm[2]][pm[3]]);
+      q += (inv % 2 ? -1.0L : 1.0L) * (long double)creal(m_trace(&prod));
+    }
+    const long double norm = 1.0L / (2.0L * 3.0L * 4.0L * 3.0L);
+    sr[x] = s_r * norm;
+    ss[x] = s_w * norm;
+    qq[x] = q / (32.0L * (long double)M_PI * (long double)M_PI);
+  }
+  ksum ksr = {0, 0}, kq = {0, 0}, ks = {0, 0};
+  for (int64_t x = 0; x < V; ++x) {
+    ks_add(&ksr, sr[x]);
+    ks_add(&kq, qq[x]);
+    ks_add(&ks, ss[x]);
+    if (sdens) sdens[x] = (double)ss[x];
+    if (qdens) qdens[x] = (double)qq[x];
+  }
+  out[0] = (double)((ksr.sum + ksr.comp) / (long double)V);
+  out[1] = (double)(kq.sum + kq.comp);
+  out[2] = (double)((ks.sum + ks.comp) / (long double)V);
+  free(sr);
+  free(qq);
+  free(ss);
+  lat_free(&g);
+  return ORA_OK;
+}
+
+/* Sec. VII, Eq. (correlation_s): <a b> / sqrt(<a^2> <b^2>) over n values. */
+double ora_correlation(int64_t n, const double *a, const double *b) {
+  ksum ab = {0, 0}, aa = {0, 0}, bb = {0, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    ks_add(&ab, (long double)a[i] * b[i]);
+    ks_add(&aa, (long double)a[i] * a[i]);
+    ks_add(&bb, (long double)b[i] * b[i]);
+  }
+  const long double sab = ab.sum + ab.comp, saa = aa.sum + aa.comp, sbb = bb.sum + bb.comp;
+  return (double)(sab / sqrtl(saa * sbb));
+}
+
 int ora_measure(const int32_t dims[4], const double *links, const int8_t *n0, ora_stats *out,
                 int8_t *flux) {
   if (!links || !n0 || !out) return ORA_E_NULL;

@@ -86,4 +86,11 @@ int ora_measure(const int32_t dims[4], const double *links, const int8_t *n0, or
                 int8_t *flux);
 int ora_sectors(const int32_t dims[4], const double *links, int8_t *out);
 
+/* Reconstructed action and topological charge from the 1x1 clover field
+ * strength: out = {<S_R>/beta, Q, <S>/beta}; sdens, qdens (nullable) receive
+ * S(x)/beta and q(x), canonical site order. */
+int ora_clover(const int32_t dims[4], const double *links, double *out, double *sdens, double *qdens);
+/* <a b> / sqrt(<a^2> <b^2>). */
+double ora_correlation(int64_t n, const double *a, const double *b);
+
 #endif
