@@ -22,7 +22,7 @@ SRC_PATH = os.path.join(_HERE, "oracle.c")
 OK, E_DIMS, E_PARAM, E_NULL = 0, -1, -2, -3
 UNDEF = -128
 JACOBI, ANNEALED = 0, 1
-STOUT, MAXRETR = 0, 1
+STOUT, MAXRETR, APE = 0, 1, 2
 
 STATS_DTYPE = np.dtype([
     ("plaq", "<f8"), ("action", "<f8"), ("max_unitarity", "<f8"), ("reserved", "<f8"),
@@ -62,6 +62,7 @@ def lib():
             "ora_generator": (None, [P, P]),
             "ora_expm": (None, [P, P]),
             "ora_maxretr": (None, [P, P, i32, P]),
+            "ora_unit_circle_projection": (None, [P, P]),
             "ora_update_link": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32,
                                                i32, i64, P, P]),
             "ora_update_links": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32,
@@ -172,7 +173,14 @@ def maxretr(u, v, loops=3) -> np.ndarray:
 
 
 def _upd(update):
-    return {"stout": STOUT, "maxretr": MAXRETR, "cooling": MAXRETR}.get(update, update)
+    return {"stout": STOUT, "maxretr": MAXRETR, "cooling": MAXRETR, "ape": APE}.get(update, update)
+
+
+def unit_circle_projection(v) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.complex128)
+    out = np.empty((3, 3), dtype=np.complex128)
+    lib().ora_unit_circle_projection(_p(v), _p(out))
+    return out
 
 
 def update_link(dims, links, n0, mu, site, *, gauge=None, update="stout", vp=False, rho=0.1,

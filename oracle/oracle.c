@@ -477,6 +477,69 @@ void ora_maxretr(const double *u, const double *v, int32_t loops, double *out) {
   m_store(&r, out);
 }
 
+/* Eigen-decomposition A = Q diag(lam) Q^dagger of a Hermitian 3x3 matrix by
+ * cyclic Jacobi rotations, each zeroing one off-diagonal pair (the complex
+ * Hermitian form of the classical method, Golub & Van Loan Sec. 8.5). */
+static void herm_eig(const mat3 *A, double lam[3], mat3 *Q) {
+  mat3 a = *A, q = m_ident();
+  static const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double m = creal(a.a[i][j] * conj(a.a[i][j]));
+        tot += m;
+        if (i != j) off += m;
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int k = 0; k < 3; ++k) {
+      const int p = pairs[k][0], r = pairs[k][1];
+      const double mag = cabs(a.a[p][r]);
+      if (mag == 0.0) continue;
+      const cplx ph = a.a[p][r] / mag;
+      const double tau = (creal(a.a[r][r]) - creal(a.a[p][p])) / (2.0 * mag);
+      const double t = fabs(tau) > 1e150 ? 0.5 / tau
+                                         : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+      const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+      mat3 J = m_ident();
+      J.a[p][p] = c;
+      J.a[p][r] = sn * ph;
+      J.a[r][p] = -sn * conj(ph);
+      J.a[r][r] = c;
+      mat3 Jd = m_dag(&J), t1 = m_mul(&Jd, &a);
+      a = m_mul(&t1, &J);
+      q = m_mul(&q, &J);
+    }
+  }
+  for (int i = 0; i < 3; ++i) lam[i] = creal(a.a[i][i]);
+  *Q = q;
+}
+
+/* Unit circle projection (Sec. II.C, Eq. W): W = V (V^dagger V)^{-1/2}, then
+ * W / cbrt(det W) with the principal cube root (arg det W in (-pi, pi], so the
+ * root's phase lies in (-pi/3, pi/3]).  The inverse square root is taken from
+ * the eigen-decomposition of V^dagger V. */
+static mat3 unit_circle_projection(const mat3 *v) {
+  mat3 vd = m_dag(v), A = m_mul(&vd, v), Q;
+  double lam[3];
+  herm_eig(&A, lam, &Q);
+  mat3 D = m_zero();
+  for (int i = 0; i < 3; ++i) D.a[i][i] = 1.0 / sqrt(lam[i]);
+  mat3 Qd = m_dag(&Q), t = m_mul(&Q, &D), isq = m_mul(&t, &Qd);
+  mat3 W = m_mul(v, &isq);
+  const cplx det = W.a[0][0] * (W.a[1][1] * W.a[2][2] - W.a[1][2] * W.a[2][1]) -
+                   W.a[0][1] * (W.a[1][0] * W.a[2][2] - W.a[1][2] * W.a[2][0]) +
+                   W.a[0][2] * (W.a[1][0] * W.a[2][1] - W.a[1][1] * W.a[2][0]);
+  const cplx root = cpow(cabs(det), 1.0 / 3.0) * cexp(I * carg(det) / 3.0);
+  return m_scale(&W, 1.0 / root);
+}
+
+void ora_unit_circle_projection(const double *v, double *out) {
+  mat3 vm = m_load(v);
+  mat3 r = unit_circle_projection(&vm);
+  m_store(&r, out);
+}
+
 /* ------------------------------------------------------- link update */
 
 typedef struct {
@@ -489,7 +552,8 @@ typedef struct {
  * accept/reject of Sec. VI.  Stout (Eq. stout): U' = exp(rho Q) U with Q from
  * Omega = Sigma U^dagger.  MaxReTr (Sec. III, Eq. V): the blocked matrix
  * V = (1 - alpha) U + (alpha/6) Sigma, then U' = MaxReTr(U, V); alpha = 1 is
- * cooling.  With vp on, U' is accepted only if it projects to the original
+ * cooling.  APE (Sec. II.C): the same V returned to SU(3) by the unit circle
+ * projection.  With vp on, U' is accepted only if it projects to the original
  * centre element n0, after undoing the gauge transform when one is given:
  * P_Z3{G^dagger(x) U' G(x + mu)} = Z.  Returns 1 if accepted. */
 static int update_link(const lattice *g, const double *links, const int8_t *n0,
@@ -508,7 +572,10 @@ static int update_link(const lattice *g, const double *links, const int8_t *n0,
     mat3 a = m_scale(&u, 1.0 - pr->alpha);
     mat3 b = m_scale(&S, pr->alpha / 6.0);
     mat3 v = m_add(&a, &b);
-    cand = maxretr(&u, &v, pr->loops);
+    if (pr->update == ORA_APE)
+      cand = unit_circle_projection(&v);
+    else
+      cand = maxretr(&u, &v, pr->loops);
   }
   if (pr->vp) {
     mat3 test = cand;
@@ -529,7 +596,7 @@ static int update_link(const lattice *g, const double *links, const int8_t *n0,
 }
 
 static int check_params(const params *pr) {
-  if (pr->update != ORA_STOUT && pr->update != ORA_MAXRETR) return 0;
+  if (pr->update != ORA_STOUT && pr->update != ORA_MAXRETR && pr->update != ORA_APE) return 0;
   if (!isfinite(pr->rho) || !isfinite(pr->eps) || !isfinite(pr->u0) || pr->u0 == 0.0) return 0;
   if (!isfinite(pr->alpha) || pr->loops < 0) return 0;
   return 1;

@@ -36,6 +36,7 @@
 #define ORA_ANNEALED 1
 #define ORA_STOUT 0
 #define ORA_MAXRETR 1
+#define ORA_APE 2
 
 typedef struct {
   double plaq;          /* <P> = (1/18V) sum_x sum_{mu<nu} Re Tr P_{mu nu}(x)      */
@@ -63,6 +64,7 @@ int ora_staple(const int32_t dims[4], const double *links, int32_t mu, int64_t s
 void ora_generator(const double *omega, double *q);
 void ora_expm(const double *x, double *e);
 void ora_maxretr(const double *u, const double *v, int32_t loops, double *out);
+void ora_unit_circle_projection(const double *v, double *out);
 
 int ora_update_link(const int32_t dims[4], const double *links, const int8_t *n0,
                     const double *gauge, int32_t update, int32_t vp, double rho, double eps,
