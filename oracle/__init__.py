@@ -68,6 +68,7 @@ def lib():
             "ora_update_links": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32,
                                                 i64, P, P, P, P]),
             "ora_clover": (ctypes.c_int, [P, P, P, P, P]),
+            "ora_flow": (ctypes.c_int, [P, P, i32, f64, f64, f64, i32]),
             "ora_correlation": (ctypes.c_double, [i64, P, P]),
             "ora_pass": (ctypes.c_int, [P, P, P, P, i32, i32, f64, f64, f64, f64, i32, i32,
                                         i32, P]),
@@ -253,6 +254,14 @@ def measure(dims, links, n0, with_flux=False):
     _check(lib().ora_measure(_p(_dims(dims)), _p(links), _p(n0), _p(st), _p(flux)), "measure")
     rec = st.view(np.recarray)[0]
     return (rec, flux) if with_flux else rec
+
+
+def flow(dims, links, n_steps, eps, *, eps_oi=1.0, u0=1.0, integrator="rk3"):
+    """Wilson flow in place on `links` (every link at once): Euler or RK3."""
+    assert links.dtype == np.complex128 and links.flags.c_contiguous
+    it = {"euler": 0, "rk3": 1}[integrator]
+    _check(lib().ora_flow(_p(_dims(dims)), _p(links), int(n_steps), float(eps), float(eps_oi), float(u0), it),
+           "flow")
 
 
 def clover(dims, links, densities=False):

@@ -767,6 +767,92 @@ int ora_smooth(const int32_t dims[4], double *links, const int8_t *n0, const dou
   return ORA_OK;
 }
 
+/* ------------------------------------------------------- Wilson flow */
+
+/* Z(W)_mu(x) = eps Q_mu(x)[W]: the flow generator of Sec. II.B (the stout
+ * generator of Eq. generator, with plain or over-improved staples), times the
+ * step, for every link of W. */
+static void flow_generators(const lattice *g, const double *w, double eps, double eps_oi, double u0,
+                            mat3 *z) {
+  const int64_t V = g->V;
+#pragma omp parallel for schedule(static) collapse(2)
+  for (int mu = 0; mu < 4; ++mu)
+    for (int64_t s = 0; s < V; ++s) {
+      mat3 u = m_link(w, g, mu, s);
+      mat3 S = staple_sum(g, w, mu, s, eps_oi, u0);
+      mat3 ud = m_dag(&u), om = m_mul(&S, &ud), q = generator(&om);
+      z[(size_t)mu * V + s] = m_scale(&q, eps);
+    }
+}
+
+/* W <- exp(X) W for every link, X = a Z + b Y (Y may be NULL). */
+static void flow_apply(const lattice *g, double *w, const mat3 *z, double a, const mat3 *y, double b) {
+  const int64_t V = g->V;
+#pragma omp parallel for schedule(static) collapse(2)
+  for (int mu = 0; mu < 4; ++mu)
+    for (int64_t s = 0; s < V; ++s) {
+      const size_t k = (size_t)mu * V + s;
+      mat3 x = m_scale(&z[k], a);
+      if (y) {
+        mat3 t = m_scale(&y[k], b);
+        x = m_add(&x, &t);
+      }
+      mat3 e = expm(&x), u = m_link(w, g, mu, s), r = m_mul(&e, &u);
+      m_store(&r, w + 18 * k);
+    }
+}
+
+/* n_steps steps of the Wilson flow dU/dtau = Q[U] U (Sec. II.B) of size eps,
+ * every link at once.  integrator 0: Euler, U <- exp(eps Q[U]) U (the
+ * simultaneous form of the stout step, Sec. V.B).  integrator 1: the
+ * third-order Runge-Kutta scheme the paper mentions (Sec. V.B; Luscher 2010):
+ *   W1 = exp(Z0/4) W0,  W2 = exp(8/9 Z1 - 17/36 Z0) W1,
+ *   U(tau + eps) = exp(3/4 Z2 - 8/9 Z1 + 17/36 Z0) W2,  Z_i = eps Q[W_i]. */
+int ora_flow(const int32_t dims[4], double *links, int32_t n_steps, double eps, double eps_oi, double u0,
+             int32_t integrator) {
+  if (!links) return ORA_E_NULL;
+  if (n_steps < 0 || !isfinite(eps) || !isfinite(eps_oi) || !isfinite(u0) || u0 == 0.0 ||
+      (integrator != 0 && integrator != 1))
+    return ORA_E_PARAM;
+  lattice g;
+  int rc = lat_init(&g, dims);
+  if (rc) return rc;
+  const size_t n = 4 * (size_t)g.V;
+  mat3 *z0 = (mat3 *)malloc(sizeof(mat3) * n);
+  mat3 *z1 = integrator ? (mat3 *)malloc(sizeof(mat3) * n) : NULL;
+  mat3 *z2 = integrator ? (mat3 *)malloc(sizeof(mat3) * n) : NULL;
+  if (!z0 || (integrator && (!z1 || !z2))) {
+    free(z0);
+    free(z1);
+    free(z2);
+    lat_free(&g);
+    return ORA_E_PARAM;
+  }
+  for (int st = 0; st < n_steps; ++st) {
+    flow_generators(&g, links, eps, eps_oi, u0, z0);
+    if (!integrator) {
+      flow_apply(&g, links, z0, 1.0, NULL, 0.0);
+      continue;
+    }
+    flow_apply(&g, links, z0, 0.25, NULL, 0.0);
+    flow_generators(&g, links, eps, eps_oi, u0, z1);
+    flow_apply(&g, links, z1, 8.0 / 9.0, z0, -17.0 / 36.0);
+    flow_generators(&g, links, eps, eps_oi, u0, z2);
+    /* 3/4 Z2 - 8/9 Z1 + 17/36 Z0 */
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < (int64_t)n; ++k) {
+      mat3 a = m_scale(&z1[k], -8.0 / 9.0), b = m_scale(&z0[k], 17.0 / 36.0);
+      z1[k] = m_add(&a, &b);
+    }
+    flow_apply(&g, links, z2, 0.75, z1, 1.0);
+  }
+  free(z0);
+  free(z1);
+  free(z2);
+  lat_free(&g);
+  return ORA_OK;
+}
+
 /* ------------------------------------------------------- measurement */
 
 /* Neumaier's compensated summation, in long double. */

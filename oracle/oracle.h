@@ -88,6 +88,11 @@ int ora_measure(const int32_t dims[4], const double *links, const int8_t *n0, or
                 int8_t *flux);
 int ora_sectors(const int32_t dims[4], const double *links, int8_t *out);
 
+/* n_steps Wilson-flow steps of size eps on every link at once; integrator 0 =
+ * Euler, 1 = third-order Runge-Kutta.  eps_oi: staple over-improvement. */
+int ora_flow(const int32_t dims[4], double *links, int32_t n_steps, double eps, double eps_oi, double u0,
+             int32_t integrator);
+
 /* Reconstructed action and topological charge from the 1x1 clover field
  * strength: out = {<S_R>/beta, Q, <S>/beta}; sdens, qdens (nullable) receive
  * S(x)/beta and q(x), canonical site order. */
