@@ -113,6 +113,15 @@ def run_gpu_form(args, precision, dims, n, pairs):
     torch.cuda.synchronize()
     durs = [evs[i].elapsed_time(evs[i + 1]) for i in range(npass)]
     avg_pass_ms = sum(durs) / len(durs)
+    # field strength of the smoothed field (Sec. V.A smoothness condition), timed
+    ce = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ce[0].record(stream)
+    for i in range(3):
+        cl = api.measure_clover(f)
+        ce[i + 1].record(stream)
+    torch.cuda.synchronize()
+    clover_ms = sum(ce[i].elapsed_time(ce[i + 1]) for i in range(3)) / 3
+    cl = cl.cpu().numpy()
     launch_lu = V // 4
     algo_bytes = launch_lu * pass_bytes_per_lu(precision)
     achieved = algo_bytes / (avg_pass_ms * 1e-3) / 1e9
@@ -123,13 +132,15 @@ def run_gpu_form(args, precision, dims, n, pairs):
         action=[float(a) for a in st.action], plaq_last=float(st.plaq[-1]),
         flux_mismatch=int(st.flux_mismatch.sum()), nonfinite=int(st.nonfinite.sum()),
         max_unitarity=float(st.max_unitarity.max()), rejected=int(st.rejected.sum()),
+        clover={"ms": round(clover_ms, 4), "sr_over_s": float(cl[0] / cl[2]), "Q": float(cl[1])},
     )
 
 
-def maxretr_form(dims, n, pairs, precision, sweeps=2, alpha=0.7):
-    """The MaxReTr update (annealed, over-improved eps = -0.25, alpha = 0.7, three
-    SU(2) loops, vortex preservation) on the same preconditioned field: its
-    subset passes timed with events, as for the stout pass."""
+def update_form(dims, n, pairs, precision, update="maxretr", sweeps=2, alpha=0.7):
+    """Another update on the same preconditioned field, annealed, over-improved
+    (eps = -0.25), alpha = 0.7, vortex preservation: MaxReTr (three SU(2)
+    loops) or APE with unit circle projection.  Its subset passes are timed with
+    events, as for the stout pass."""
     import torch
 
     from paper_2203_09764_amd import api
@@ -137,7 +148,7 @@ def maxretr_form(dims, n, pairs, precision, sweeps=2, alpha=0.7):
     f = api.Field(dims, precision, device="cuda:0", jacobi_workspace=False)
     f.set_charges(n)
     api.precondition(f, pairs, 0.02)
-    kw = dict(update="maxretr", alpha=alpha, vp=True)
+    kw = dict(update=update, alpha=alpha, vp=True)
     for mu in range(4):  # one untimed sweep
         for colour in (0, 2, 1, 3):
             api.anneal_pass(f, mu, colour, 0.0, -0.25, **kw)
@@ -156,10 +167,35 @@ def maxretr_form(dims, n, pairs, precision, sweeps=2, alpha=0.7):
     avg = sum(durs) / len(durs)
     st = api.stats_to_numpy(api.measure(f), 1)[0]
     lu = f.V // 4
-    return {"update": "MaxReTr alpha=%g, 3 SU(2) loops, eps=-0.25, vortex preservation" % alpha,
+    label = "MaxReTr, 3 SU(2) loops" if update == "maxretr" else "APE, unit circle projection"
+    return {"update": "%s, alpha=%g, eps=-0.25, vortex preservation" % (label, alpha),
             "avg_pass_ms": round(avg, 4), "lu_per_s": round(lu / (avg * 1e-3), 1),
             "hbm_frac": round(lu * pass_bytes_per_lu(precision) / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "flux_mismatch": int(st.flux_mismatch)}
+
+
+def flow_form(dims, n, pairs, precision, steps=2, eps=0.02):
+    """Third-order Runge-Kutta Wilson flow (every link at once, plain staples)
+    on the preconditioned field: the time of one step (3 stages, 12 launches)."""
+    import torch
+
+    from paper_2203_09764_amd import api
+
+    f = api.Field(dims, precision, device="cuda:0", jacobi_workspace=False)
+    f.set_charges(n)
+    api.precondition(f, pairs, 0.02)
+    api.flow(f, 1, eps, integrator="rk3")  # untimed, allocates its workspace once
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    api.flow(f, steps, eps, integrator="rk3")
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    return {"update": "Wilson flow, third-order Runge-Kutta, eps=%g, plain staples" % eps,
+            "ms_per_step": round(ms, 3), "link_updates_per_s": round(3 * 4 * f.V / (ms * 1e-3), 1)}
 
 
 def serving_leg(n_jobs: int, rate: float, slots: int = 64, seed: int = 3):
@@ -284,13 +320,16 @@ def main():
                         "avg_pass_ms": round(r["avg_pass_ms"], 4),
                         "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
                         "flux_mismatch": r["flux_mismatch"], "nonfinite": r["nonfinite"],
-                        "max_unitarity": r["max_unitarity"], "final_action": r["action"][-1]}
+                        "max_unitarity": r["max_unitarity"], "final_action": r["action"][-1],
+                        "clover_measure": r["clover"]}
     if "fp64" in res and "fp32_bulk" in res:
         a64, a32 = res["fp64"]["action"], res["fp32_bulk"]["action"]
         forms_out["fp32_bulk"]["speedup_vs_fp64"] = round(res["fp32_bulk"]["lu_per_s"] / res["fp64"]["lu_per_s"], 3)
         forms_out["fp32_bulk"]["max_rel_action_dev_vs_fp64"] = max(abs(x - y) / abs(y) for x, y in zip(a32, a64))
     for p in forms:
-        forms_out[p + "_maxretr"] = maxretr_form(dims, n, pairs, p)
+        for upd in ("maxretr", "ape"):
+            forms_out[p + "_" + upd] = update_form(dims, n, pairs, p, upd)
+        forms_out[p + "_flow_rk3"] = flow_form(dims, n, pairs, p)
     out["forms"] = forms_out
     if args.serving_jobs > 0:
         out["serving"] = serving_leg(args.serving_jobs, args.serving_rate, args.serving_slots)

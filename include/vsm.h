@@ -62,6 +62,8 @@ extern "C" {
 #define VSM_STOUT 0    /* U' = exp(rho Q) U (Eq. stout, Eq. generator)                */
 #define VSM_MAXRETR 1  /* MaxReTr of V = (1-alpha) U + alpha/6 Sigma (Sec. III);
                           alpha = 1 is cooling                                        */
+#define VSM_APE 2      /* APE: the same V returned to SU(3) by the unit circle
+                          projection V (V^dag V)^{-1/2} / cbrt(det) (Sec. II.C)        */
 
 /* How a sweep updates links. */
 typedef struct {
@@ -70,7 +72,7 @@ typedef struct {
   int32_t vp;        /* 1: vortex-preserving accept/reject of Sec. VI                 */
   int32_t su2_loops; /* MaxReTr: loops over the three SU(2) subgroups (paper: 3)      */
   double u0;         /* mean link in the rectangle weight of Eq. (over-improvement)  */
-  double alpha;      /* MaxReTr: APE blocking fraction of Eq. (V)                     */
+  double alpha;      /* MaxReTr and APE: blocking fraction of Eq. (V)                 */
 } vsm_schedule;
 
 /* One measurement record (64 bytes, host or device). */
@@ -171,6 +173,40 @@ int vsm_pass(const int32_t dims[4], int32_t precision, void *links_dev, const in
 int vsm_measure(const int32_t dims[4], int32_t precision, const void *links_dev, const int8_t *z3_dev,
                 void *workspace_dev, size_t workspace_bytes, vsm_stats *stats_dev,
                 int8_t *flux_dev, void *stream);
+
+/* Sec. II.B, V.B: n_steps steps of size eps of the Wilson flow
+ * dU/dtau = Q[U] U, every link at once (Q the stout generator with staples of
+ * over-improvement eps_oi, u0 as for vsm_smooth).  VSM_EULER: U <- exp(eps Q) U
+ * (the simultaneous stout step).  VSM_RK3: the third-order Runge-Kutta scheme
+ * W1 = exp(Z0/4) W0, W2 = exp(8/9 Z1 - 17/36 Z0) W1,
+ * U(tau + eps) = exp(3/4 Z2 - 8/9 Z1 + 17/36 Z0) W2 with Z_i = eps Q[W_i].
+ * workspace_dev: at least vsm_flow_workspace_bytes (a second link buffer, and
+ * for RK3 an FP64 accumulator of 8 reals per link). */
+#define VSM_EULER 0
+#define VSM_RK3 1
+size_t vsm_flow_workspace_bytes(const int32_t dims[4], int32_t precision, int32_t integrator);
+int vsm_flow(const int32_t dims[4], int32_t precision, void *links_dev, void *workspace_dev,
+             size_t workspace_bytes, int32_t n_steps, double eps, double eps_oi, double u0, int32_t integrator,
+             void *stream);
+
+/* Sec. V, Eqs. (1LFST), (1LTopQ) and the reconstructed action of Sec. V.A,
+ * with g = 1: the 1x1 clover C_{mu nu}(x) (mean of the four plaquettes of the
+ * plane that start and end at x), F_{mu nu} = (C - C^dag)/(2i) (no trace
+ * removed, as written), q(x) = eps_{mu nu rho sigma} Tr[F_{mu nu} F_{rho sigma}] /
+ * (32 pi^2), S_R(x)/beta = sum over the six planes of Tr[F F] / 72.
+ * out_dev (device, 4 doubles) = {<S_R>/beta, Q = sum_x q(x), <S>/beta, 0};
+ * the smoothness condition of Sec. V.A compares <S_R> with <S>.  sdens_dev and
+ * qdens_dev (device float64 [V], canonical site order, nullable) receive
+ * S(x)/beta and q(x).  Arithmetic in FP64 for both precisions.  Uses the
+ * reduction slots of the workspace. */
+int vsm_measure_clover(const int32_t dims[4], int32_t precision, const void *links_dev, void *workspace_dev,
+                       size_t workspace_bytes, double *out_dev, double *sdens_dev, double *qdens_dev,
+                       void *stream);
+
+/* Sec. VII, Eq. (correlation_s): out_dev (device, 4 doubles) =
+ * {<a b>/sqrt(<a^2> <b^2>), sum a b, sum a^2, sum b^2} over n device doubles
+ * (for example two action or charge densities).  n > 0. */
+int vsm_correlate(int64_t n, const double *a_dev, const double *b_dev, double *out_dev, void *stream);
 
 /* ------------------------------------------------------------------ serving
  *

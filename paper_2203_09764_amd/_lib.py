@@ -17,7 +17,7 @@ E_DIMS, E_PARAM, E_NULL, E_WORKSPACE, E_BUDGET, E_HIP, E_STATE, E_TIMEOUT = -1, 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 FP64, FP32_BULK = 0, 1
 JACOBI, ANNEALED = 0, 1
-STOUT, MAXRETR = 0, 1
+STOUT, MAXRETR, APE = 0, 1, 2
 UNDEF = -128
 
 STATS_DTYPE = np.dtype([
@@ -111,6 +111,10 @@ def lib():
 
 
 SIGNATURES.update({
+    "vsm_flow_workspace_bytes": (_sz, [Dims, _i32, _i32]),
+    "vsm_flow": (ctypes.c_int, [Dims, _i32, _P, _P, _sz, _i32, _f64, _f64, _f64, _i32, _P]),
+    "vsm_measure_clover": (ctypes.c_int, [Dims, _i32, _P, _P, _sz, _P, _P, _P, _P]),
+    "vsm_correlate": (ctypes.c_int, [_i64, _P, _P, _P, _P]),
     "vsm_server_job_bytes": (_sz, [ctypes.POINTER(Job)]),
     "vsm_server_host_bytes": (_sz, [ctypes.POINTER(Job)]),
     "vsm_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),

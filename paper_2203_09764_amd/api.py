@@ -12,12 +12,13 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (ANNEALED, FP32_BULK, FP64, JACOBI, MAXRETR, STATS_BYTES, STATS_DTYPE, STOUT,
+from ._lib import (ANNEALED, APE, FP32_BULK, FP64, JACOBI, MAXRETR, STATS_BYTES, STATS_DTYPE, STOUT,
                    Schedule, check, dims_arg, lib)
 
 PRECISIONS = {"fp64": FP64, "fp32_bulk": FP32_BULK, "fp32": FP32_BULK, FP64: FP64, FP32_BULK: FP32_BULK}
 ORDERS = {"jacobi": JACOBI, "annealed": ANNEALED, JACOBI: JACOBI, ANNEALED: ANNEALED}
-UPDATES = {"stout": STOUT, "maxretr": MAXRETR, "cooling": MAXRETR, STOUT: STOUT, MAXRETR: MAXRETR}
+UPDATES = {"stout": STOUT, "maxretr": MAXRETR, "cooling": MAXRETR, "ape": APE, STOUT: STOUT, MAXRETR: MAXRETR,
+           APE: APE}
 
 
 def _ptr(t):
@@ -180,3 +181,35 @@ def set_links(field: Field, canon, stream=None):
         raise ValueError(f"links must have shape (4, {field.V}, 3, 3)")
     check(lib().vsm_set_links(dims_arg(field.dims), field.precision, _ptr(c), _ptr(field.links),
                               _stream(stream)), "vsm_set_links")
+
+
+def measure_clover(field: Field, densities=False, stream=None):
+    """Sec. V / V.A: device float64 tensor {<S_R>/beta, Q, <S>/beta, 0}; with
+    densities also S(x)/beta and q(x) as device float64 [V] (canonical order)."""
+    out = torch.zeros(4, dtype=torch.float64, device=field.device)
+    sd = torch.empty(field.V, dtype=torch.float64, device=field.device) if densities else None
+    qd = torch.empty(field.V, dtype=torch.float64, device=field.device) if densities else None
+    check(lib().vsm_measure_clover(dims_arg(field.dims), field.precision, _ptr(field.links), _ptr(field.workspace),
+                                   field.workspace.numel(), _ptr(out), _ptr(sd), _ptr(qd), _stream(stream)),
+          "vsm_measure_clover")
+    return (out, sd, qd) if densities else out
+
+
+def correlate(a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
+    """Sec. VII: device float64 {<ab>/sqrt(<a^2><b^2>), sum ab, sum a^2, sum b^2}."""
+    if a.dtype != torch.float64 or b.dtype != torch.float64 or a.numel() != b.numel():
+        raise ValueError("expected two float64 device tensors of the same size")
+    out = torch.zeros(4, dtype=torch.float64, device=a.device)
+    check(lib().vsm_correlate(a.numel(), _ptr(a.contiguous()), _ptr(b.contiguous()), _ptr(out), _stream(stream)),
+          "vsm_correlate")
+    return out
+
+
+def flow(field: Field, n_steps, eps, *, eps_oi=1.0, u0=1.0, integrator="rk3", stream=None):
+    """Sec. II.B / V.B: n_steps Wilson-flow steps of size eps, every link at once
+    (vsm_flow); integrator "euler" or "rk3".  Allocates its workspace."""
+    it = {"euler": 0, "rk3": 1}[integrator]
+    nb = int(lib().vsm_flow_workspace_bytes(dims_arg(field.dims), field.precision, it))
+    ws = torch.empty(nb, dtype=torch.uint8, device=field.device)
+    check(lib().vsm_flow(dims_arg(field.dims), field.precision, _ptr(field.links), _ptr(ws), nb, int(n_steps),
+                         float(eps), float(eps_oi), float(u0), it, _stream(stream)), "vsm_flow")

@@ -202,4 +202,65 @@ int vsm_measure(const int32_t dims[4], int32_t precision, const void* links_dev,
   return hip_status();
 }
 
+size_t vsm_flow_workspace_bytes(const int32_t dims[4], int32_t precision, int32_t integrator) {
+  if (check_dims_impl(dims, VSM_JACOBI, precision) != VSM_OK) return 0;
+  if (integrator != VSM_EULER && integrator != VSM_RK3) return 0;
+  const WsLayout w = ws_layout(dims, precision, VSM_JACOBI);
+  const Geo g = make_geo(dims);
+  return w.total + (integrator == VSM_RK3 ? align256(8ull * 4ull * g.V * sizeof(double)) : 0);
+}
+
+int vsm_flow(const int32_t dims[4], int32_t precision, void* links_dev, void* workspace_dev, size_t workspace_bytes,
+             int32_t n_steps, double eps, double eps_oi, double u0, int32_t integrator, void* stream) {
+  int rc = check_dims_impl(dims, VSM_JACOBI, precision);
+  if (rc) return rc;
+  if (!links_dev || !workspace_dev) return VSM_E_NULL;
+  if (n_steps < 0 || !is_fin(eps) || !is_fin(eps_oi) || !is_fin(u0) || u0 == 0.0) return VSM_E_PARAM;
+  if (integrator != VSM_EULER && integrator != VSM_RK3) return VSM_E_PARAM;
+  if (workspace_bytes < vsm_flow_workspace_bytes(dims, precision, integrator)) return VSM_E_WORKSPACE;
+  const WsLayout w = ws_layout(dims, precision, VSM_JACOBI);
+  const Geo g = make_geo(dims);
+  hipStream_t st = (hipStream_t)stream;
+  const double cp = (5.0 - 2.0 * eps_oi) / 3.0, cr = (eps_oi - 1.0) / (12.0 * u0 * u0);
+  char* ws = (char*)workspace_dev;
+  double* acc = integrator == VSM_RK3 ? (double*)(ws + w.total) : nullptr;
+  void* cur = links_dev;
+  void* other = ws + w.field;
+  for (int k = 0; k < n_steps; ++k) {
+    const int stages = integrator == VSM_RK3 ? 3 : 1;
+    for (int sg = 0; sg < stages; ++sg) {
+      launch_flow(precision, g, cur, other, acc, integrator == VSM_RK3 ? sg + 1 : 0, eps, cp, cr, st);
+      void* t = cur;
+      cur = other;
+      other = t;
+    }
+  }
+  if (cur != links_dev) {
+    const hipError_t e =
+        hipMemcpyAsync(links_dev, cur, 24ull * g.V * entry_bytes(precision), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return note_hip_error(e);
+  }
+  return hip_status();
+}
+
+int vsm_measure_clover(const int32_t dims[4], int32_t precision, const void* links_dev, void* workspace_dev,
+                       size_t workspace_bytes, double* out_dev, double* sdens_dev, double* qdens_dev,
+                       void* stream) {
+  int rc = check_dims_impl(dims, VSM_JACOBI, precision);
+  if (rc) return rc;
+  if (!links_dev || !workspace_dev || !out_dev) return VSM_E_NULL;
+  const WsLayout w = ws_layout(dims, precision, VSM_ANNEALED);
+  if (workspace_bytes < w.total) return VSM_E_WORKSPACE;
+  launch_clover(precision, make_geo(dims), links_dev, (char*)workspace_dev + w.partials, out_dev, sdens_dev,
+                qdens_dev, (hipStream_t)stream);
+  return hip_status();
+}
+
+int vsm_correlate(int64_t n, const double* a_dev, const double* b_dev, double* out_dev, void* stream) {
+  if (!a_dev || !b_dev || !out_dev) return VSM_E_NULL;
+  if (n <= 0) return VSM_E_PARAM;
+  launch_correlate((long long)n, a_dev, b_dev, out_dev, (hipStream_t)stream);
+  return hip_status();
+}
+
 }  // extern "C"

@@ -113,9 +113,10 @@ inline WsLayout ws_layout(const int32_t dims[4], int32_t precision, int32_t orde
 inline int check_sched(const vsm_schedule* s) {
   if (!s) return VSM_E_NULL;
   if (s->order != VSM_JACOBI && s->order != VSM_ANNEALED) return VSM_E_PARAM;
-  if (s->update != VSM_STOUT && s->update != VSM_MAXRETR) return VSM_E_PARAM;
+  if (s->update != VSM_STOUT && s->update != VSM_MAXRETR && s->update != VSM_APE) return VSM_E_PARAM;
   if (!is_fin(s->u0) || s->u0 == 0.0) return VSM_E_PARAM;
   if (s->update == VSM_MAXRETR && (!is_fin(s->alpha) || s->su2_loops < 0)) return VSM_E_PARAM;
+  if (s->update == VSM_APE && !is_fin(s->alpha)) return VSM_E_PARAM;
   return VSM_OK;
 }
 
@@ -127,7 +128,7 @@ inline UpdParams make_params(double rho, double eps, const vsm_schedule* s) {
   p.cr = (eps - 1.0) / (12.0 * s->u0 * s->u0);
   p.rho = rho;
   p.alpha = s->alpha;
-  p.update = s->update == VSM_MAXRETR ? 1 : 0;
+  p.update = s->update == VSM_MAXRETR ? 1 : (s->update == VSM_APE ? 2 : 0);
   p.oi = p.cr != 0.0 ? 1 : 0;
   p.vp = s->vp ? 1 : 0;
   p.loops = s->su2_loops;

@@ -20,6 +20,10 @@ void launch_update_t(const Geo&, const void*, void*, const int8_t*, const void*,
 template <typename R>
 void launch_update_batch_t(const ServeJob*, const BatchStep&, uint32_t, hipStream_t);
 template <typename R>
+void launch_clover_t(const Geo&, const void*, void*, double*, double*, double*, hipStream_t);
+template <typename R>
+void launch_flow_t(const Geo&, const void*, void*, double*, int, double, double, double, hipStream_t);
+template <typename R>
 void launch_measure_t(const Geo&, const void*, const int8_t*, void*, int8_t*, unsigned long long*,
                       VsmStatsDev*, long long, hipStream_t);
 
@@ -91,6 +95,68 @@ void launch_update_batch(int prec, const ServeJob* jobs_dev, const BatchStep& st
                          hipStream_t st) {
   if (prec == 0) launch_update_batch_t<double>(jobs_dev, step, nblocks, st);
   else launch_update_batch_t<float>(jobs_dev, step, nblocks, st);
+}
+
+void launch_flow(int prec, const Geo& g, const void* src, void* dst, double* acc, int stage, double eps,
+                 double cp, double cr, hipStream_t st) {
+  if (prec == 0) launch_flow_t<double>(g, src, dst, acc, stage, eps, cp, cr, st);
+  else launch_flow_t<float>(g, src, dst, acc, stage, eps, cp, cr, st);
+}
+
+void launch_clover(int prec, const Geo& g, const void* links, void* partials, double* out, double* sdens,
+                   double* qdens, hipStream_t st) {
+  if (prec == 0) launch_clover_t<double>(g, links, partials, out, sdens, qdens, st);
+  else launch_clover_t<float>(g, links, partials, out, sdens, qdens, st);
+}
+
+// <a b> / sqrt(<a^2> <b^2>) with Neumaier sums: one block, a fixed stride per
+// thread and a fixed-order tree, so the result does not depend on scheduling.
+__device__ __forceinline__ void nsum(double& s, double& c, double v) {
+  const double t = s + v;
+  if (fabs(s) >= fabs(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
+__global__ void __launch_bounds__(1024) k_correlate(long long n, const double* __restrict__ a,
+                                                    const double* __restrict__ b, double* out) {
+  double v[6] = {0, 0, 0, 0, 0, 0};  // ab, aa, bb sums and compensations
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double x = a[i], y = b[i];
+    nsum(v[0], v[1], x * y);
+    nsum(v[2], v[3], x * x);
+    nsum(v[4], v[5], y * y);
+  }
+  __shared__ double sh[6][1024];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int stride = 512; stride > 0; stride >>= 1) {
+    if ((int)threadIdx.x < stride) {
+#pragma unroll
+      for (int k = 0; k < 6; k += 2) {
+        double s = sh[k][threadIdx.x], c = sh[k + 1][threadIdx.x];
+        nsum(s, c, sh[k][threadIdx.x + stride]);
+        c += sh[k + 1][threadIdx.x + stride];
+        sh[k][threadIdx.x] = s;
+        sh[k + 1][threadIdx.x] = c;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double ab = sh[0][0] + sh[1][0], aa = sh[2][0] + sh[3][0], bb = sh[4][0] + sh[5][0];
+    out[0] = ab / sqrt(aa * bb);
+    out[1] = ab;
+    out[2] = aa;
+    out[3] = bb;
+  }
+}
+
+void launch_correlate(long long n, const double* a, const double* b, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_correlate, dim3(1), dim3(1024), 0, st, n, a, b, out);
 }
 
 // Block partials written by the measurement kernel: 10 eight-byte fields.

@@ -310,13 +310,11 @@ __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm,
 
 // ------------------------------------------------------------------ updates
 
-// Stout (Eq. stout, Eq. generator): Omega = Sigma U^dag, Q its traceless
-// anti-Hermitian part (diagonal from differences so that an Omega proportional
-// to 1 gives exactly Q = 0), X = rho Q, U' = exp(X) U via Cayley-Hamilton with
-// FP64 coefficients, then FP64 reunitarisation.  Q = 0 returns U unchanged.
+// H = -i rho Q for the stout generator Q of Omega = Sigma U^dag: Hermitian and
+// traceless, the diagonal from differences (exactly 0 for Omega proportional
+// to 1).
 template <typename R>
-__device__ __forceinline__ bool stout_candidate(const M3<R>& S, const M3<R>& U, double rho,
-                                                M3<double>& out) {
+__device__ __forceinline__ M3<R> stout_h(const M3<R>& S, const M3<R>& U, double rho) {
   const M3<R> om = mul_nd(S, U);
   // A = (Omega - Omega^dag)/2 ; Q_ij = A_ij off the diagonal; diagonal A_ii is i*a_i
   const R a0 = om.a[0].im, a1 = om.a[4].im, a2 = om.a[8].im;
@@ -339,6 +337,13 @@ __device__ __forceinline__ bool stout_candidate(const M3<R>& S, const M3<R>& U, 
       H.a[3 * i + j] = cx<R>(r * ai, -r * ar);
       H.a[3 * j + i] = cx<R>(r * ai, r * ar);
     }
+  return H;
+}
+
+// out = exp(i H) U for Hermitian traceless H, by Cayley-Hamilton with FP64
+// coefficients, then FP64 reunitarisation.  H = 0 returns false (U unchanged).
+template <typename R>
+__device__ __forceinline__ bool exp_apply(const M3<R>& H, const M3<R>& U, M3<double>& out) {
   double c0, c1;
   ch_invariants(H, c0, c1);
   if (c1 == 0.0) return false;
@@ -362,6 +367,14 @@ __device__ __forceinline__ bool stout_candidate(const M3<R>& S, const M3<R>& U, 
   out = mconvert<double>(mul_nn(E, U));
   reunitarise(out);
   return true;
+}
+
+// Stout (Eq. stout, Eq. generator): Omega = Sigma U^dag, Q its traceless
+// anti-Hermitian part, X = rho Q, U' = exp(X) U.  Q = 0 returns U unchanged.
+template <typename R>
+__device__ __forceinline__ bool stout_candidate(const M3<R>& S, const M3<R>& U, double rho,
+                                                M3<double>& out) {
+  return exp_apply(stout_h(S, U, rho), U, out);
 }
 
 // MaxReTr (Eq. maxReTr, def_L1, def_T1): V = (1 - alpha) U + (alpha/6) Sigma,
@@ -426,6 +439,83 @@ __device__ __forceinline__ bool maxretr_candidate(const M3<R>& S, const M3<R>& U
   return moved;
 }
 
+// APE (Sec. II.C, Eqs. V, W): the blocked matrix V = (1 - alpha) U +
+// (alpha/6) Sigma in FP64, returned to SU(3) by the unit circle projection:
+// its unitary polar factor W, by the scaled Newton iteration
+// X <- (z X + X^{-dagger}/z)/2 with z = sqrt(|X^{-1}|_F / |X|_F) (Higham), then
+// W / cbrt(det W) with the principal root (phase in (-pi/3, pi/3]), and an
+// FP64 Gram-Schmidt clean-up.  A singular V has no projection (NaN, counted as
+// non-finite by the measurement).
+template <typename R>
+__device__ __forceinline__ bool ape_candidate(const M3<R>& S, const M3<R>& U0, double alpha, M3<double>& out) {
+  const M3<double> U = mconvert<double>(U0);
+  const M3<double> Sd = mconvert<double>(S);
+  M3<double> X;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    X.a[e].re = (1.0 - alpha) * U.a[e].re + alpha / 6.0 * Sd.a[e].re;
+    X.a[e].im = (1.0 - alpha) * U.a[e].im + alpha / 6.0 * Sd.a[e].im;
+  }
+  auto cmul = [](Cx<double> a, Cx<double> b) { return cx<double>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); };
+  auto adj_det = [&](const M3<double>& m, M3<double>& adj) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const Cx<double> p = cmul(m.a[3 * ((j + 1) % 3) + (i + 1) % 3], m.a[3 * ((j + 2) % 3) + (i + 2) % 3]);
+        const Cx<double> q = cmul(m.a[3 * ((j + 1) % 3) + (i + 2) % 3], m.a[3 * ((j + 2) % 3) + (i + 1) % 3]);
+        adj.a[3 * i + j] = cx<double>(p.re - q.re, p.im - q.im);
+      }
+    Cx<double> d = cx<double>(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const Cx<double> t = cmul(m.a[j], adj.a[3 * j]);
+      d.re += t.re;
+      d.im += t.im;
+    }
+    return d;
+  };
+  auto fro = [](const M3<double>& m) {
+    double r = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) r += m.a[e].re * m.a[e].re + m.a[e].im * m.a[e].im;
+    return sqrt(r);
+  };
+#pragma unroll 1
+  for (int it = 0; it < 20; ++it) {
+    M3<double> adj;
+    const Cx<double> d = adj_det(X, adj);
+    const double dd = d.re * d.re + d.im * d.im;
+    // X^{-1} = adj / d; X^{-dagger} = adj^dagger / conj(d) = adj^dagger d / |d|^2
+    const double nx = fro(X), ni = fro(adj) / sqrt(dd);
+    const double z = sqrt(ni / nx);
+    double diff = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const Cx<double> a = adj.a[3 * j + i];  // (adj^dagger)_ij = conj(adj_ji)
+        const Cx<double> inv_dag = cmul(cx<double>(a.re, -a.im), d);
+        const Cx<double> x = X.a[3 * i + j];
+        const Cx<double> y = cx<double>(0.5 * (z * x.re + inv_dag.re / (z * dd)),
+                                        0.5 * (z * x.im + inv_dag.im / (z * dd)));
+        diff += (y.re - x.re) * (y.re - x.re) + (y.im - x.im) * (y.im - x.im);
+        X.a[3 * i + j] = y;
+      }
+    if (!(diff > 1e-28 * 3.0)) break;  // |X|_F = sqrt 3 at convergence; NaN stops too
+  }
+  M3<double> adj;
+  const Cx<double> d = adj_det(X, adj);
+  const double r = cbrt(sqrt(d.re * d.re + d.im * d.im));
+  const double ph = atan2(d.im, d.re) / 3.0;
+  const Cx<double> inv_root = cx<double>(cos(ph) / r, -sin(ph) / r);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) X.a[e] = cmul(X.a[e], inv_root);
+  reunitarise(X);
+  out = X;
+  return true;
+}
+
 // Tr[G^dagger(x) U G(x + mu)]: the trace the vortex-preservation test projects
 // when the field lives in the random gauge G (Sec. VI).
 __device__ __noinline__ Cx<double> gauge_undone_trace(const double2* __restrict__ gauge, uint32_t s0,
@@ -437,6 +527,48 @@ __device__ __noinline__ Cx<double> gauge_undone_trace(const double2* __restrict_
     Gp.a[e] = cx<double>(gauge[(size_t)s1 * 9 + e].x, gauge[(size_t)s1 * 9 + e].y);
   }
   return mtrace(mul_nn(mul_dn(G, u), Gp));
+}
+
+// Sigma of link (x, MU) from the field src (Eq. plaq_staples; with OI the
+// over-improved sum of Eq. over-improvement, in the factored form with
+// U_mu(x +- mu) loaded once).
+template <typename R, int MU, bool OI>
+__device__ __forceinline__ M3<R> staple_sum(const Geo& g, const void* src, const int c[4], uint32_t x, R cp,
+                                            R cr) {
+  const DirBuf<R> bm = dir_buf<R>(src, g, MU);
+  Nb o;
+  o.S = (c[0] + c[1] + c[2] + c[3]) & 3;
+  o.j = x - (uint32_t)o.S * g.V4;
+  o.dm[0] = jdelta(g, MU, c[MU], -1);
+  o.dm[1] = 0;
+  o.dm[2] = jdelta(g, MU, c[MU], 1);
+  o.dm[3] = jdelta(g, MU, c[MU], 2);
+  M3<R> S = mzero<R>();
+  M3<R> K, Lm;
+  if (OI) {
+    K = ld_rows(bm, nbi(g, o, 1, 0));
+    load_fence();
+    Lm = ld_rows(bm, nbi(g, o, -1, 0));
+    load_fence();
+  }
+#pragma unroll 1
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == MU) continue;
+    o.dn[0] = jdelta(g, nu, c[nu], -2);
+    o.dn[1] = jdelta(g, nu, c[nu], -1);
+    o.dn[2] = 0;
+    o.dn[3] = jdelta(g, nu, c[nu], 1);
+    o.dn[4] = jdelta(g, nu, c[nu], 2);
+    const DirBuf<R> bn = dir_buf<R>(src, g, nu);
+    if (OI) {
+      staple_dir_shared<R, true>(S, bm, bn, g, o, cp, cr, K, Lm);
+      staple_dir_shared<R, false>(S, bm, bn, g, o, cp, cr, K, Lm);
+    } else {
+      staple_dir<R, OI, true>(S, bm, bn, g, o, cp, cr);
+      staple_dir<R, OI, false>(S, bm, bn, g, o, cp, cr);
+    }
+  }
+  return S;
 }
 
 // The thread's link of an annealing subset (Sec. III.A masking).  Subset c of
@@ -490,49 +622,16 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
   bool rej = false;
   if (active) {
     const uint32_t x = site_index(g, c);
-    const R cp = (R)p.cp, cr = (R)p.cr;
-    const DirBuf<R> bm = dir_buf<R>(src, g, MU);
-    Nb o;
-    o.S = (c[0] + c[1] + c[2] + c[3]) & 3;
-    o.j = x - (uint32_t)o.S * g.V4;
-    o.dm[0] = jdelta(g, MU, c[MU], -1);
-    o.dm[1] = 0;
-    o.dm[2] = jdelta(g, MU, c[MU], 1);
-    o.dm[3] = jdelta(g, MU, c[MU], 2);
-    M3<R> S = mzero<R>();
-    // over-improved staples: the factored form with U_mu(x +- mu) loaded once
-    constexpr bool kShared = OI;
-    M3<R> K, Lm;
-    if (kShared) {
-      K = ld_rows(bm, nbi(g, o, 1, 0));
-      load_fence();
-      Lm = ld_rows(bm, nbi(g, o, -1, 0));
-      load_fence();
-    }
-#pragma unroll 1
-    for (int nu = 0; nu < 4; ++nu) {
-      if (nu == MU) continue;
-      o.dn[0] = jdelta(g, nu, c[nu], -2);
-      o.dn[1] = jdelta(g, nu, c[nu], -1);
-      o.dn[2] = 0;
-      o.dn[3] = jdelta(g, nu, c[nu], 1);
-      o.dn[4] = jdelta(g, nu, c[nu], 2);
-      const DirBuf<R> bn = dir_buf<R>(src, g, nu);
-      if (kShared) {
-        staple_dir_shared<R, true>(S, bm, bn, g, o, cp, cr, K, Lm);
-        staple_dir_shared<R, false>(S, bm, bn, g, o, cp, cr, K, Lm);
-      } else {
-        staple_dir<R, OI, true>(S, bm, bn, g, o, cp, cr);
-        staple_dir<R, OI, false>(S, bm, bn, g, o, cp, cr);
-      }
-    }
-    const M3<R> U = ld_link(bm, x);
+    const M3<R> S = staple_sum<R, MU, OI>(g, src, c, x, (R)p.cp, (R)p.cr);
+    const M3<R> U = ld_link(dir_buf<R>(src, g, MU), x);
     M3<double> cand;
     bool moved;
     if (UPD == 0)
       moved = stout_candidate<R>(S, U, p.rho, cand);
-    else
+    else if (UPD == 1)
       moved = maxretr_candidate<R>(S, U, p.alpha, p.loops, cand);
+    else
+      moved = ape_candidate<R>(S, U, p.alpha, cand);
     // the candidate exactly as a later load will see it: rows 0 and 1 rounded
     // to the storage precision, row 2 rebuilt from them
     M3<R> cr_ = mconvert<R>(cand);
@@ -632,6 +731,60 @@ __global__ void __launch_bounds__(256) k_update_batch(const ServeJob* __restrict
   }
   const unsigned long long m = __ballot(rej);
   if ((threadIdx.x & 63u) == 0u && m) atomicAdd(J.rej, (unsigned long long)__popcll(m));
+}
+
+// ------------------------------------------------------------------ Wilson flow
+
+// One stage of the Wilson flow (Sec. II.B, V.B) for every link of direction MU,
+// from the field src into dst (all links at once).  H_Z = -i eps Q[src] is the
+// step's generator (the stout generator with rho = eps); acc holds the
+// Runge-Kutta accumulator H_A (FP64, 8 reals per link: H_00, H_11 and the
+// upper triangle).  Stage 0: Euler, H = H_Z.  Stages 1-3: the third-order
+// scheme W1 = exp(Z0/4) W0, W2 = exp(8/9 Z1 - 17/36 Z0) W1,
+// W3 = exp(3/4 Z2 - 8/9 Z1 + 17/36 Z0) W2, kept with one accumulator:
+// stage 1 H = H_Z/4, A <- H; stage 2 H = 8/9 H_Z - 17/9 A, A <- H;
+// stage 3 H = 3/4 H_Z - A.  dst = exp(i H) src, reunitarised.
+template <typename R, int MU, bool OI>
+__global__ void __launch_bounds__(256) k_flow(Geo g, const void* src, void* dst, double* __restrict__ acc,
+                                              int stage, double eps, double cp, double cr) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.V) return;
+  int c[4];
+  coords_of_index(g, t, c);
+  const M3<R> S = staple_sum<R, MU, OI>(g, src, c, t, (R)cp, (R)cr);
+  const M3<R> U = ld_link(dir_buf<R>(src, g, MU), t);
+  const M3<R> Hz = stout_h(S, U, eps);
+  M3<R> H = Hz;
+  if (stage > 0) {
+    double* a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = acc + ((size_t)k * 4 + MU) * g.V + t;
+    double hz[8] = {(double)Hz.a[0].re, (double)Hz.a[4].re, (double)Hz.a[1].re, (double)Hz.a[1].im,
+                    (double)Hz.a[2].re, (double)Hz.a[2].im, (double)Hz.a[5].re, (double)Hz.a[5].im};
+    double h[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (stage == 1)
+        h[k] = 0.25 * hz[k];
+      else if (stage == 2)
+        h[k] = (8.0 / 9.0) * hz[k] - (17.0 / 9.0) * *a[k];
+      else
+        h[k] = 0.75 * hz[k] - *a[k];
+      if (stage < 3) *a[k] = h[k];
+    }
+    H.a[0] = cx<R>((R)h[0], R(0));
+    H.a[4] = cx<R>((R)h[1], R(0));
+    H.a[8] = cx<R>((R)(-h[0] - h[1]), R(0));
+    H.a[1] = cx<R>((R)h[2], (R)h[3]);
+    H.a[3] = cx<R>((R)h[2], (R)(-h[3]));
+    H.a[2] = cx<R>((R)h[4], (R)h[5]);
+    H.a[6] = cx<R>((R)h[4], (R)(-h[5]));
+    H.a[5] = cx<R>((R)h[6], (R)h[7]);
+    H.a[7] = cx<R>((R)h[6], (R)(-h[7]));
+  }
+  M3<double> out;
+  if (!exp_apply(H, U, out)) out = mconvert<double>(U);
+  st_link<R>(dst, g, MU, t, mconvert<R>(out));
 }
 
 // ------------------------------------------------------------------ measurement
@@ -854,6 +1007,188 @@ __global__ void __launch_bounds__(256) k_finalize(const Partial* __restrict__ pa
   }
 }
 
+// ------------------------------------------------------------------ field strength
+
+// The 1x1 clover C_{mu nu}(x) (internal directions dm, dn): the mean of the
+// four plaquettes of the plane that start and end at x, each in the mu -> nu
+// sense; FP64.
+template <typename R>
+__device__ __forceinline__ M3<double> clover_at(const Geo& g, const void* links, const int c[4], int dm,
+                                                int dn) {
+  const DirBuf<R> bm = dir_buf<R>(links, g, dm), bn = dir_buf<R>(links, g, dn);
+  auto at = [&](int a, int b) {
+    int e[4] = {c[0], c[1], c[2], c[3]};
+    e[dm] = wrap_add(e[dm], a, g.L[dm]);
+    e[dn] = wrap_add(e[dn], b, g.L[dn]);
+    return site_index(g, e);
+  };
+  auto L = [&](const DirBuf<R>& b, uint32_t i) {
+    const M3<double> m = mconvert<double>(ld_link(b, i));
+    load_fence();
+    return m;
+  };
+  // full 3x3 products: links stored in FP32 are unitary only to FP32 rounding,
+  // so a row rebuilt from two others would not be the product's own
+  M3<double> C = mzero<double>();
+  M3<double> t;
+  // U_mu(x) U_nu(x+mu) U_mu^dag(x+nu) U_nu^dag(x)
+  t = mul_nn(L(bm, at(0, 0)), L(bn, at(1, 0)));
+  t = mul_nd(t, L(bm, at(0, 1)));
+  t = mul_nd(t, L(bn, at(0, 0)));
+  maxpy(C, 0.25, t);
+  // U_nu(x) U_mu^dag(x-mu+nu) U_nu^dag(x-mu) U_mu(x-mu)
+  t = mul_nd(L(bn, at(0, 0)), L(bm, at(-1, 1)));
+  t = mul_nd(t, L(bn, at(-1, 0)));
+  t = mul_nn(t, L(bm, at(-1, 0)));
+  maxpy(C, 0.25, t);
+  // U_mu^dag(x-mu) U_nu^dag(x-mu-nu) U_mu(x-mu-nu) U_nu(x-nu)
+  t = madj(mul_nn(L(bn, at(-1, -1)), L(bm, at(-1, 0))));
+  t = mul_nn(t, L(bm, at(-1, -1)));
+  t = mul_nn(t, L(bn, at(0, -1)));
+  maxpy(C, 0.25, t);
+  // U_nu^dag(x-nu) U_mu(x-nu) U_nu(x+mu-nu) U_mu^dag(x)
+  t = mul_dn(L(bn, at(0, -1)), L(bm, at(0, -1)));
+  t = mul_nn(t, L(bn, at(1, -1)));
+  t = mul_nd(t, L(bm, at(0, 0)));
+  maxpy(C, 0.25, t);
+  return C;
+}
+
+// F = (C - C^dag) / (2i), Hermitian (no trace removed).
+__device__ __forceinline__ M3<double> field_strength(const M3<double>& C) {
+  M3<double> F;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const Cx<double> a = C.a[3 * i + j], b = C.a[3 * j + i];
+      F.a[3 * i + j] = cx<double>(0.5 * (a.im + b.im), -0.5 * (a.re - b.re));
+    }
+  return F;
+}
+
+// Re Tr[F G].
+__device__ __forceinline__ double retr_prod(const M3<double>& F, const M3<double>& G) {
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      r = fma(F.a[3 * i + j].re, G.a[3 * j + i].re, r);
+      r = fma(-F.a[3 * i + j].im, G.a[3 * j + i].im, r);
+    }
+  return r;
+}
+
+struct ClovPartial {  // 80 bytes, the size of a measurement partial
+  double sr_s, sr_c, q_s, q_c, s_s, s_c, pad[4];
+};
+static_assert(sizeof(ClovPartial) == 80, "clover partials share the measurement slots");
+
+// Per site (Sec. V, Eqs. 1LFST, 1LTopQ; the reconstructed action of Sec. V.A):
+// F for the six planes from the clover, S_R(x)/beta = (1/72) sum_{mu<nu}
+// Tr[F F], q(x) = 1/(32 pi^2) eps Tr[F F] = (1/4 pi^2) Re Tr[F01 F23 - F02 F13
+// + F03 F12] (user axes), and S(x)/beta = (2/72) sum_{mu<nu} Re Tr[1 - P]
+// with P the first clover leaf.  Densities (canonical order) when asked for;
+// fixed-slot block partials as in k_measure.
+template <typename R>
+__global__ void __launch_bounds__(256) k_clover(Geo g, const void* links, ClovPartial* __restrict__ part,
+                                                double* __restrict__ sdens, double* __restrict__ qdens) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  KSum ksr = {0.0, 0.0}, kq = {0.0, 0.0}, ks = {0.0, 0.0};
+  if (t < g.V) {
+    int c[4];
+    coords_of_index(g, t, c);
+    double sr = 0.0, q = 0.0, sw = 0.0;
+    // plane pairs (01, 23), (02, 13), (03, 12) with signs +, -, +
+#pragma unroll 1
+    for (int pr = 0; pr < 3; ++pr) {
+      const int a0 = 0, a1 = pr + 1;
+      const int b0 = pr == 0 ? 2 : 1, b1 = pr == 2 ? 2 : 3;
+      const M3<double> Fa = field_strength(clover_at<R>(g, links, c, g.perm[a0], g.perm[a1]));
+      const M3<double> Fb = field_strength(clover_at<R>(g, links, c, g.perm[b0], g.perm[b1]));
+      sr += retr_prod(Fa, Fa) + retr_prod(Fb, Fb);
+      q += (pr == 1 ? -1.0 : 1.0) * retr_prod(Fa, Fb);
+    }
+    // Wilson action density from the plaquettes at x
+#pragma unroll 1
+    for (int plane = 0; plane < 6; ++plane) {
+      const int mu = plane < 3 ? 0 : (plane < 5 ? 1 : 2);
+      const int nu = plane < 3 ? plane + 1 : (plane < 5 ? plane - 1 : 3);
+      const int dm = g.perm[mu], dn = g.perm[nu];
+      int cm[4] = {c[0], c[1], c[2], c[3]};
+      cm[dm] = wrap_add(cm[dm], 1, g.L[dm]);
+      int cn[4] = {c[0], c[1], c[2], c[3]};
+      cn[dn] = wrap_add(cn[dn], 1, g.L[dn]);
+      const DirBuf<R> bmu = dir_buf<R>(links, g, dm), bnu = dir_buf<R>(links, g, dn);
+      M3<double> P = mul_nn(mconvert<double>(ld_link(bmu, t)), mconvert<double>(ld_link(bnu, site_index(g, cm))));
+      load_fence();
+      P = mul_nd(P, mconvert<double>(ld_link(bmu, site_index(g, cn))));
+      load_fence();
+      P = mul_nd(P, mconvert<double>(ld_link(bnu, t)));
+      load_fence();
+      sw += (1.0 - P.a[0].re) + (1.0 - P.a[4].re) + (1.0 - P.a[8].re);
+    }
+    const double norm = 1.0 / 72.0;
+    sr *= norm;
+    sw *= 2.0 * norm;
+    q *= 1.0 / (4.0 * 3.14159265358979323846 * 3.14159265358979323846);
+    kadd(ksr, sr);
+    kadd(kq, q);
+    kadd(ks, sw);
+    const uint32_t s = canonical_index(g, c);
+    if (sdens) sdens[s] = sw;
+    if (qdens) qdens[s] = q;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    kmerge(ksr, KSum{__shfl_xor(ksr.s, off), __shfl_xor(ksr.c, off)});
+    kmerge(kq, KSum{__shfl_xor(kq.s, off), __shfl_xor(kq.c, off)});
+    kmerge(ks, KSum{__shfl_xor(ks.s, off), __shfl_xor(ks.c, off)});
+  }
+  __shared__ ClovPartial w[4];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) w[wave] = ClovPartial{ksr.s, ksr.c, kq.s, kq.c, ks.s, ks.c, {0, 0, 0, 0}};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    KSum a = {w[0].sr_s, w[0].sr_c}, b = {w[0].q_s, w[0].q_c}, d = {w[0].s_s, w[0].s_c};
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+      kmerge(a, KSum{w[i].sr_s, w[i].sr_c});
+      kmerge(b, KSum{w[i].q_s, w[i].q_c});
+      kmerge(d, KSum{w[i].s_s, w[i].s_c});
+    }
+    part[blockIdx.x] = ClovPartial{a.s, a.c, b.s, b.c, d.s, d.c, {0, 0, 0, 0}};
+  }
+}
+
+// Fixed-order reduction of the clover partials into {<S_R>/beta, Q, <S>/beta}.
+template <typename R>
+__global__ void __launch_bounds__(256) k_clover_finalize(const ClovPartial* __restrict__ part, uint32_t nparts,
+                                                         double inv_v, double* out) {
+  KSum a = {0.0, 0.0}, b = {0.0, 0.0}, d = {0.0, 0.0};
+  for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+    kmerge(a, KSum{part[i].sr_s, part[i].sr_c});
+    kmerge(b, KSum{part[i].q_s, part[i].q_c});
+    kmerge(d, KSum{part[i].s_s, part[i].s_c});
+  }
+  __shared__ KSum sh[3][256];
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = d;
+  __syncthreads();
+  for (int stride = 128; stride > 0; stride >>= 1) {
+    if ((int)threadIdx.x < stride)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) kmerge(sh[k][threadIdx.x], sh[k][threadIdx.x + stride]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = (sh[0][0].s + sh[0][0].c) * inv_v;
+    out[1] = sh[1][0].s + sh[1][0].c;
+    out[2] = (sh[2][0].s + sh[2][0].c) * inv_v;
+    out[3] = 0.0;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -904,15 +1239,21 @@ void launch_update_mu(const Geo& g, const void* src, void* dst, const int8_t* z3
     if (p.update == 0)
       hipLaunchKernelGGL((k_update<R, MU, true, 0>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
                          colour, jacobi, n, rej);
-    else
+    else if (p.update == 1)
       hipLaunchKernelGGL((k_update<R, MU, true, 1>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
+                         colour, jacobi, n, rej);
+    else
+      hipLaunchKernelGGL((k_update<R, MU, true, 2>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
                          colour, jacobi, n, rej);
   } else {
     if (p.update == 0)
       hipLaunchKernelGGL((k_update<R, MU, false, 0>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
                          colour, jacobi, n, rej);
-    else
+    else if (p.update == 1)
       hipLaunchKernelGGL((k_update<R, MU, false, 1>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
+                         colour, jacobi, n, rej);
+    else
+      hipLaunchKernelGGL((k_update<R, MU, false, 2>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
                          colour, jacobi, n, rej);
   }
 }
@@ -934,6 +1275,36 @@ void launch_update_batch_t(const ServeJob* jobs, const BatchStep& step, uint32_t
   // the same cap on resident blocks per CU as for single-field passes
   const unsigned lds = sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u;
   hipLaunchKernelGGL(k_update_batch<R>, dim3(nblocks), dim3(256), lds, st, jobs, step);
+}
+
+template <typename R, int MU>
+void launch_flow_mu(const Geo& g, const void* src, void* dst, double* acc, int stage, double eps, double cp,
+                    double cr, hipStream_t st) {
+  const unsigned nb = blocks_for(g.V, 256);
+  if (cr != 0.0) {
+    const unsigned lds = sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u;
+    hipLaunchKernelGGL((k_flow<R, MU, true>), dim3(nb), dim3(256), lds, st, g, src, dst, acc, stage, eps, cp, cr);
+  } else {
+    hipLaunchKernelGGL((k_flow<R, MU, false>), dim3(nb), dim3(256), 0, st, g, src, dst, acc, stage, eps, cp, cr);
+  }
+}
+
+template <typename R>
+void launch_flow_t(const Geo& g, const void* src, void* dst, double* acc, int stage, double eps, double cp,
+                   double cr, hipStream_t st) {
+  launch_flow_mu<R, 0>(g, src, dst, acc, stage, eps, cp, cr, st);
+  launch_flow_mu<R, 1>(g, src, dst, acc, stage, eps, cp, cr, st);
+  launch_flow_mu<R, 2>(g, src, dst, acc, stage, eps, cp, cr, st);
+  launch_flow_mu<R, 3>(g, src, dst, acc, stage, eps, cp, cr, st);
+}
+
+template <typename R>
+void launch_clover_t(const Geo& g, const void* links, void* partials, double* out, double* sdens,
+                     double* qdens, hipStream_t st) {
+  const unsigned nb = blocks_for(g.V, 256);
+  hipLaunchKernelGGL(k_clover<R>, dim3(nb), dim3(256), 0, st, g, links, (ClovPartial*)partials, sdens, qdens);
+  hipLaunchKernelGGL(k_clover_finalize<R>, dim3(1), dim3(256), 0, st, (const ClovPartial*)partials, nb,
+                     1.0 / (double)g.V, out);
 }
 
 template <typename R>

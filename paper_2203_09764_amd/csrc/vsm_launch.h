@@ -15,7 +15,7 @@ struct UpdParams {
   double cr;     // rectangle weight (eps - 1)/(12 u0^2)
   double rho;    // stout step
   double alpha;  // APE blocking fraction (MaxReTr)
-  int update;    // 0 stout, 1 MaxReTr
+  int update;    // 0 stout, 1 MaxReTr, 2 APE with unit circle projection
   int oi;        // rectangles present (eps != 1)
   int vp;        // vortex-preserving accept/reject
   int loops;     // MaxReTr subgroup loops
@@ -72,6 +72,16 @@ void launch_update_batch(int prec, const ServeJob* jobs_dev, const BatchStep& st
 // Charges z3 (canonical layout) into out (internal layout, 4V bytes) for the
 // internal directions d0 .. d0 + nd - 1.
 void launch_charges(const Geo& g, const int8_t* z3, int8_t* out, int d0, int nd, hipStream_t st);
+// One Wilson-flow stage (0 Euler, 1..3 Runge-Kutta) of all four directions
+// from src into dst; acc: the FP64 accumulator, 8 x 4V doubles.
+void launch_flow(int prec, const Geo& g, const void* src, void* dst, double* acc, int stage, double eps,
+                 double cp, double cr, hipStream_t st);
+// Clover field strength: {<S_R>/beta, Q, <S>/beta, 0} into out (device), the
+// densities S(x)/beta and q(x) (canonical order) when not null.
+void launch_clover(int prec, const Geo& g, const void* links, void* partials, double* out, double* sdens,
+                   double* qdens, hipStream_t st);
+// {<ab>/sqrt(<a^2><b^2>), <ab>, <a^2>, <b^2>} (sums, not means) into out.
+void launch_correlate(long long n, const double* a, const double* b, double* out, hipStream_t st);
 void launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 
 }  // namespace vsm

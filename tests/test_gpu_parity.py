@@ -291,3 +291,55 @@ def test_vp_maxretr_leaves_a_z3_field_unchanged(dims, alpha):
     else:
         assert int(st.rejected[0]) > 0
     assert int(st.flux_mismatch[0]) == 0
+
+
+@pytest.mark.parametrize("order,alpha,eps", [("jacobi", 0.7, 1.0), ("jacobi", 0.3, -0.25),
+                                             ("annealed", 0.7, -0.25)])
+def test_ape_unit_circle_projection_full_su3(order, alpha, eps):
+    """APE with unit circle projection (Sec. II.C) on a random-gauge
+    preconditioned field: two sweeps against the oracle (its projection by a
+    Jacobi eigen-decomposition, the GPU's by the scaled Newton polar
+    iteration)."""
+    dims = (8, 8, 4, 8)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 51)
+    pairs = fieldgen.centrifuge_pairs(dims, 52)
+    G = fieldgen.haar_su3(fieldgen.volume(dims), 53)
+    U = ora.gauge_transform(dims, ora.centrifuge(dims, n, pairs, 0.02), G)
+    f = _field(dims)
+    f.set_charges(n)
+    api.set_links(f, torch.from_numpy(U))
+    st = api.smooth(f, 2, 0.0, eps, order=order, update="ape", alpha=alpha, measure_every=1)
+    so = ora.smooth(dims, U, n, 2, order=order, update="ape", alpha=alpha, eps=eps)
+    np.testing.assert_allclose(_stats(st, 2).plaq, so.plaq, rtol=1e-12, atol=0)
+    assert np.abs(_links(f) - U).max() < LINK_TOL
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", LINK_TOL), ("fp32_bulk", 2e-6)])
+def test_ape_maps_a_vortex_field_to_centre_elements(precision, tol):
+    """The paper's result for APE on a Z(3) field: every link is mapped to a
+    centre element again (in MCG), the one the oracle picks.  Where the phase of
+    the scalar blocked matrix lies exactly on a boundary between two centre
+    elements (possible here, since it is a sum of cube roots of unity) the
+    principal cube root is not defined and rounding decides; such ties are
+    excluded from the comparison (and must be rare)."""
+    dims = (8, 8, 8, 8)
+    n = fieldgen.z3_vortex_charges(dims, 0.3, 54)
+    f = _field(dims, precision)
+    f.set_charges(n)
+    api.load_z3(f, n)
+    api.smooth(f, 1, 0.0, -0.25, order="jacobi", update="ape", alpha=0.7)
+    got = _links(f)
+    U0 = ora.z3_field(dims, n)
+    U = U0.copy()
+    ora.smooth(dims, U, n, 1, order="jacobi", update="ape", alpha=0.7, eps=-0.25, measure_every=0)
+    # centre elements: diagonal, equal entries, a cube root of unity
+    d = got[..., [0, 1, 2], [0, 1, 2]]
+    assert np.abs(got - d[..., None] * np.eye(3)).max() < tol
+    assert np.abs(d ** 3 - 1).max() < 3 * tol
+    bad = np.argwhere(np.abs(got - U).max(axis=(2, 3)) >= tol)
+    assert len(bad) < 0.01 * got.shape[0] * got.shape[1]
+    for mu, s in bad:
+        Vb = 0.3 * U0[mu, s] + 0.7 / 6 * ora.staple(dims, U0, int(mu), int(s), eps=-0.25)
+        th = np.angle(np.trace(Vb) / 3)
+        r = (th + np.pi / 3) % (2 * np.pi / 3)  # 0 on a boundary
+        assert min(r, 2 * np.pi / 3 - r) < 1e-9, (mu, s, th)
