@@ -260,6 +260,7 @@ def main():
     ap.add_argument("--pass-sweeps", type=int, default=4, help="sweeps timed pass by pass for the roofline")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the MaxReTr, APE and flow legs")
     ap.add_argument("--serving-jobs", type=int, default=200, help="jobs of the serving stream (0: skip)")
     ap.add_argument("--serving-rate", type=float, default=50.0, help="mean arrivals per second")
     ap.add_argument("--serving-slots", type=int, default=64, help="jobs resident at once")
@@ -326,7 +327,7 @@ def main():
         a64, a32 = res["fp64"]["action"], res["fp32_bulk"]["action"]
         forms_out["fp32_bulk"]["speedup_vs_fp64"] = round(res["fp32_bulk"]["lu_per_s"] / res["fp64"]["lu_per_s"], 3)
         forms_out["fp32_bulk"]["max_rel_action_dev_vs_fp64"] = max(abs(x - y) / abs(y) for x, y in zip(a32, a64))
-    for p in forms:
+    for p in ([] if args.no_forms else forms):
         for upd in ("maxretr", "ape"):
             forms_out[p + "_" + upd] = update_form(dims, n, pairs, p, upd)
         forms_out[p + "_flow_rk3"] = flow_form(dims, n, pairs, p)
