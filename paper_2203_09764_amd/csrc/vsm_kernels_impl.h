@@ -255,54 +255,48 @@ __device__ __forceinline__ void staple_dir(M3<R>& S, const DirBuf<R>& bm, const 
 // The same paths with every distinct link loaded once per orientation (10
 // loads instead of 18) and the plaquette staple sharing A B with the 2x1 path
 // whose site x sits at the left; K = U_mu(x+mu) and L = U_mu(x-mu) are common to
-// all nu and loaded once by the caller.  Links used more than once are held as
-// rows 0 and 1 and completed per use, which keeps the FP64 form within 256
-// VGPRs.
+// all nu and loaded once by the caller.  Links are loaded as rows 0 and 1 and
+// completed per use; each load is issued two products ahead of its first use,
+// so that two links are in flight while a product runs (the fences keep the
+// compiler from hoisting more loads than that, which would spill).
 template <typename R, bool UP>
 __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm, const DirBuf<R>& bn,
                                                   const Geo& g, const Nb& o, R cp, R cr,
                                                   const M3<R>& K, const M3<R>& L) {
   auto I = [&](int a, int b) { return nbi(g, o, a, b); };
   const int sg = UP ? 1 : -1;
-  // A, B, C are used several times: held as rows 0 and 1, completed per use
-  const M3<R> Ar = ld_rows(bn, I(0, UP ? 0 : -1));
-  load_fence();
-  const M3<R> Cr = ld_rows(bn, I(1, UP ? 0 : -1));
-  load_fence();
   // 1x2: A D E F^dag C^dag
-  M3<R> w;
-  {
-    const M3<R> Dr = ld_link(bn, I(0, UP ? 1 : -2));
-    load_fence();
-    w = UP ? mul2_nn(Ar, Dr) : mul2_dd(full(Ar), Dr);
-  }
-  chain_step<R, false>(w, bm, I(0, 2 * sg));
-  {
-    const M3<R> Fr = ld_link(bn, I(1, UP ? 1 : -2));
-    load_fence();
-    w = UP ? mul2_nd(w, Fr) : mul2_nn(w, Fr);
-  }
+  const M3<R> Ar = ld_rows(bn, I(0, UP ? 0 : -1));
+  const M3<R> Cr = ld_rows(bn, I(1, UP ? 0 : -1));
+  const M3<R> Dr = ld_rows(bn, I(0, UP ? 1 : -2));
+  const M3<R> Er = ld_rows(bm, I(0, 2 * sg));
+  load_fence();
+  const M3<R> Fr = ld_rows(bn, I(1, UP ? 1 : -2));
+  load_fence();
+  M3<R> w = UP ? mul2_nn(Ar, full(Dr)) : mul2_dd(full(Ar), full(Dr));
+  const M3<R> Br = ld_rows(bm, I(0, sg));
+  load_fence();
+  w = mul2_nn(w, full(Er));
+  const M3<R> Gr = ld_rows(bm, I(1, sg));
+  load_fence();
+  w = UP ? mul2_nd(w, full(Fr)) : mul2_nn(w, full(Fr));
   w = UP ? mul2_nd(w, full(Cr)) : mul2_nn(w, full(Cr));
   chain_add(S, cr, w);
   // plaquette A B C^dag and 2x1 left A B G H^dag K^dag share T = A B
-  const M3<R> Br = ld_rows(bm, I(0, sg));
+  const M3<R> Hr = ld_rows(bn, I(2, UP ? 0 : -1));
   load_fence();
   M3<R> T = UP ? mul2_nn(Ar, full(Br)) : mul2_dn(full(Ar), full(Br));
   chain_add(S, cp, UP ? mul2_nd(T, full(Cr)) : mul2_nn(T, full(Cr)));
-  chain_step<R, false>(T, bm, I(1, sg));
-  {
-    const M3<R> Hr = ld_link(bn, I(2, UP ? 0 : -1));
-    load_fence();
-    T = UP ? mul2_nd(T, Hr) : mul2_nn(T, Hr);
-  }
+  const M3<R> Mr = ld_rows(bn, I(-1, UP ? 0 : -1));
+  load_fence();
+  T = mul2_nn(T, full(Gr));
+  const M3<R> Nr = ld_rows(bm, I(-1, sg));
+  load_fence();
+  T = UP ? mul2_nd(T, full(Hr)) : mul2_nn(T, full(Hr));
   chain_add(S, cr, mul2_nd(T, full(K)));
   // 2x1 middle: L^dag M N B C^dag
-  {
-    const M3<R> Mr = ld_link(bn, I(-1, UP ? 0 : -1));
-    load_fence();
-    w = UP ? mul2_dn(full(L), Mr) : mul2_dd(full(L), Mr);
-  }
-  chain_step<R, false>(w, bm, I(-1, sg));
+  w = UP ? mul2_dn(full(L), full(Mr)) : mul2_dd(full(L), full(Mr));
+  w = mul2_nn(w, full(Nr));
   w = mul2_nn(w, full(Br));
   w = UP ? mul2_nd(w, full(Cr)) : mul2_nn(w, full(Cr));
   chain_add(S, cr, w);
@@ -666,21 +660,38 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
 
 // One update step for direction MU over the whole lattice (see update_one);
 // rejections are counted per wave into *rejected.
+// XCD-aware block order: consecutive hardware blocks go round-robin to the 8
+// XCDs; this gives each XCD one contiguous range of the lattice (when the grid
+// is a multiple of 8 blocks), so that neighbouring blocks share an L2.
+__device__ __forceinline__ uint32_t xcd_block() {
+  const uint32_t b = blockIdx.x, nb = gridDim.x;
+  return (nb & 7u) == 0u ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+}
+
+// Site of a thread of the measurement kernels (blocks of 256).  Block b takes
+// a chunk of 64 positions j (rows of internal axis 0 in the tile order of the
+// update) and its four waves take the four sublattices of that chunk: a wave's
+// loads of a link entry are one contiguous run, and the neighbour x + mu of a
+// site (the next sublattice) is read by another wave of the same block.
+// Returns false for threads past the end of the lattice.
+__device__ __forceinline__ bool chunk_site(const Geo& g, uint32_t b, int c[4]) {
+  const uint32_t tj = b * 64u + (threadIdx.x & 63u);
+  if (tj >= g.V4) return false;
+  const uint32_t s = (threadIdx.x >> 6) & 3u;
+  const uint32_t row = tj / (uint32_t)g.Xq;
+  const uint32_t xi = tj - row * (uint32_t)g.Xq;
+  tile_rows(g, row, c, 0);
+  c[0] = (int)(4u * xi) + (int)((s - (uint32_t)(c[1] + c[2] + c[3])) & 3u);
+  return true;
+}
+
 template <typename R, int MU, bool OI, int UPD>
 __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* dst,
                                                 const int8_t* __restrict__ z3,
                                                 const double2* __restrict__ gauge, UpdParams p,
                                                 int colour, int jacobi, uint32_t nthreads,
                                                 unsigned long long* __restrict__ rejected) {
-  // XCD-aware block order: consecutive hardware blocks go round-robin to the 8
-  // XCDs; give each XCD one contiguous range of the lattice.
-  uint32_t b = blockIdx.x;
-  const uint32_t nb = gridDim.x;
-#ifndef VSM_XCD_REMAP
-#define VSM_XCD_REMAP 1
-#endif
-  if (VSM_XCD_REMAP && (nb & 7u) == 0u) b = (b & 7u) * (nb >> 3) + (b >> 3);
-  const uint32_t t = b * blockDim.x + threadIdx.x;
+  const uint32_t t = xcd_block() * blockDim.x + threadIdx.x;
   const bool rej = update_one<R, MU, OI, UPD>(g, src, dst, z3, gauge, p, colour, jacobi, t, nthreads);
   if (rejected) {
     const unsigned long long m = __ballot(rej);
@@ -821,20 +832,20 @@ __device__ __forceinline__ int link_sector(const M3<double>& u) {
 // Re Tr P and Re Tr[1 - P] (Sec. V.A); the sectors of the four links at x;
 // the vortex flux of every plaquette from the link sectors compared with the
 // flux of the original charges; unitarity and finiteness of the own links.
-// Threads run over the internal site index; planes use user axes; the
-// original charges z3 are in the internal layout (k_charges).  Block partials
-// go to fixed slots; k_finalize sums them in a fixed order, so
-// the result does not depend on the scheduling.
+// Sites by chunk_site, blocks in XCD ranges, so the neighbours x + mu of a
+// site are read by the same or a nearby block and come from cache.
+// Planes use user axes; the original charges z3 are in the internal layout
+// (k_charges).  Block partials go to fixed slots; k_finalize sums them in a
+// fixed order, so the result does not depend on the scheduling.
 template <typename R>
 __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const int8_t* __restrict__ z3,
                                                  Partial* __restrict__ part, int8_t* __restrict__ flux) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t blk = xcd_block();
   KSum kp = {0.0, 0.0}, ka = {0.0, 0.0};
-  double maxu = 0.0;
+  double maxu2 = 0.0;  // largest |(U^dag U - 1)_ij|^2; its root is taken once per thread
   long long mism = 0, undef = 0, nonfin = 0;
-  if (t < g.V) {
-    int c[4];
-    coords_of_index(g, t, c);
+  int c[4];
+  if (chunk_site(g, blk, c)) {
     const uint32_t x = site_index(g, c);
     const uint32_t s = canonical_index(g, c);
     // original charges of the four links at x (user directions), one byte each;
@@ -856,64 +867,72 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
 #pragma unroll
       for (int e = 0; e < 9; ++e) {
         const double dr = uu.a[e].re - ((e % 4 == 0) ? 1.0 : 0.0);
-        const double dv = sqrt(dr * dr + uu.a[e].im * uu.a[e].im);
-        maxu = fmax(maxu, dv);
+        maxu2 = fmax(maxu2, fma(dr, dr, uu.a[e].im * uu.a[e].im));
       }
     };
-    // planes 01, 02, 03, 12, 13, 23 (user axes), mu outer so that A = U_mu(x)
-    // is read once per mu; D = U_nu(x) is read per plane (from cache after
-    // its first read)
+    // planes 01, 02, 03, 12, 13, 23 (user axes); the four links of a plaquette
+    // are loaded together (rows 0 and 1), so one memory latency is exposed per
+    // plane; the own links of x come from cache after their first read
 #pragma unroll 1
-    for (int mu = 0; mu < 3; ++mu) {
-      const int dm = g.perm[mu];
-      const DirBuf<R> bmu = dir_buf<R>(links, g, dm);
-      const M3<double> A = mconvert<double>(ld_link(bmu, x));
+    for (int p = 0; p < 6; ++p) {
+      const int mu = p < 3 ? 0 : (p < 5 ? 1 : 2);
+      const int nu = p < 3 ? p + 1 : (p < 5 ? p - 1 : 3);
+      const int dm = g.perm[mu], dn = g.perm[nu];
+      const DirBuf<R> bmu = dir_buf<R>(links, g, dm), bnu = dir_buf<R>(links, g, dn);
+      int cm[4] = {c[0], c[1], c[2], c[3]};
+      cm[dm] = wrap_add(cm[dm], 1, g.L[dm]);
+      int cn[4] = {c[0], c[1], c[2], c[3]};
+      cn[dn] = wrap_add(cn[dn], 1, g.L[dn]);
+      const uint32_t xm = site_index(g, cm), xn = site_index(g, cn);
+      const M3<R> Ar = ld_rows(bmu, x);
+      const M3<R> Br = ld_rows(bnu, xm);
+      const M3<R> Cr = ld_rows(bmu, xn);
+      const M3<R> Dr = ld_rows(bnu, x);
       load_fence();
-      if (mu == 0) own_checks(A, 0);
-      int cn[4];
-#pragma unroll 1
-      for (int nu = mu + 1; nu < 4; ++nu) {
-        const int plane = mu == 0 ? nu - 1 : (mu == 1 ? nu + 1 : 5);
-        const int dn = g.perm[nu];
-        const DirBuf<R> bnu = dir_buf<R>(links, g, dn);
-        int cm[4] = {c[0], c[1], c[2], c[3]};
-        cm[dm] = wrap_add(cm[dm], 1, g.L[dm]);
+      const M3<double> A = mconvert<double>(full(Ar));
+      if (p == 0) own_checks(A, 0);
+      const M3<double> B = mconvert<double>(full(Br));
+      const int sb = link_sector(B);
+      M3<double> P = mul_nn(A, B);
+      const M3<double> Cm = mconvert<double>(full(Cr));
+      const int sc = link_sector(Cm);
+      P = mul_nd(P, Cm);
+      const M3<double> D = mconvert<double>(full(Dr));
+      if (mu == 0) own_checks(D, nu);
+      // only the diagonal of P D^dag is needed: Re (P D^dag)_ii = sum_k Re P_ik conj(D_ik)
+      double dg[3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) cn[k] = c[k];
-        cn[dn] = wrap_add(cn[dn], 1, g.L[dn]);
-        const M3<double> B = mconvert<double>(ld_link(bnu, site_index(g, cm)));
-        load_fence();
-        const int sb = link_sector(B);
-        M3<double> P = mul_nn(A, B);
-        const M3<double> Cm = mconvert<double>(ld_link(bmu, site_index(g, cn)));
-        load_fence();
-        const int sc = link_sector(Cm);
-        P = mul_nd(P, Cm);
-        const M3<double> D = mconvert<double>(ld_link(bnu, x));
-        load_fence();
-        if (mu == 0) own_checks(D, nu);
-        P = mul_nd(P, D);
-        const double rt = P.a[0].re + P.a[4].re + P.a[8].re;
-        const double ra = (1.0 - P.a[0].re) + (1.0 - P.a[4].re) + (1.0 - P.a[8].re);
-        kadd(kp, rt);
-        kadd(ka, ra);
-        const int smu = byte_at(secb, mu), snu = byte_at(secb, nu);
-        const int o = byte_at(n0b, mu) + (int)z3[(size_t)dn * g.V + site_index(g, cm)] -
-                      (int)z3[(size_t)dm * g.V + site_index(g, cn)] - byte_at(n0b, nu);
-        const int orig = ((o % 3) + 3) % 3;
-        int pv;
-        if (smu == kUndef || sb == kUndef || sc == kUndef || snu == kUndef) {
-          ++mism;
-          pv = kUndef;
-        } else {
-          const int r = (((smu + sb - sc - snu) % 3) + 3) % 3;
-          if (r != orig) ++mism;
-          pv = (r == 2) ? -1 : r;
+      for (int i = 0; i < 3; ++i) {
+        double v = P.a[3 * i].re * D.a[3 * i].re;
+        v = fma(P.a[3 * i].im, D.a[3 * i].im, v);
+#pragma unroll
+        for (int k = 1; k < 3; ++k) {
+          v = fma(P.a[3 * i + k].re, D.a[3 * i + k].re, v);
+          v = fma(P.a[3 * i + k].im, D.a[3 * i + k].im, v);
         }
-        if (flux) flux[(size_t)plane * g.V + s] = (int8_t)pv;
+        dg[i] = v;
       }
+      const double rt = dg[0] + dg[1] + dg[2];
+      const double ra = (1.0 - dg[0]) + (1.0 - dg[1]) + (1.0 - dg[2]);
+      kadd(kp, rt);
+      kadd(ka, ra);
+      const int smu = byte_at(secb, mu), snu = byte_at(secb, nu);
+      const int o = byte_at(n0b, mu) + (int)z3[(size_t)dn * g.V + xm] - (int)z3[(size_t)dm * g.V + xn] -
+                    byte_at(n0b, nu);
+      const int orig = ((o % 3) + 3) % 3;
+      int pv;
+      if (smu == kUndef || sb == kUndef || sc == kUndef || snu == kUndef) {
+        ++mism;
+        pv = kUndef;
+      } else {
+        const int r = (((smu + sb - sc - snu) % 3) + 3) % 3;
+        if (r != orig) ++mism;
+        pv = (r == 2) ? -1 : r;
+      }
+      if (flux) flux[(size_t)p * g.V + s] = (int8_t)pv;
     }
   }
+  double maxu = sqrt(maxu2);
   // wave reduction (fixed butterfly), then a fixed-order pass over the 4 waves
   for (int off = 32; off > 0; off >>= 1) {
     KSum op = {__shfl_xor(kp.s, off), __shfl_xor(kp.c, off)};
@@ -946,7 +965,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
     r.plaq_c = a.c;
     r.act_s = bsum.s;
     r.act_c = bsum.c;
-    part[blockIdx.x] = r;
+    part[blk] = r;
   }
 }
 
@@ -1011,10 +1030,11 @@ __global__ void __launch_bounds__(256) k_finalize(const Partial* __restrict__ pa
 
 // The 1x1 clover C_{mu nu}(x) (internal directions dm, dn): the mean of the
 // four plaquettes of the plane that start and end at x, each in the mu -> nu
-// sense; FP64.
+// sense; FP64.  The first leaf is the plaquette P_{mu nu}(x) itself; wilson
+// receives Re Tr[1 - P] of it.
 template <typename R>
 __device__ __forceinline__ M3<double> clover_at(const Geo& g, const void* links, const int c[4], int dm,
-                                                int dn) {
+                                                int dn, double& wilson) {
   const DirBuf<R> bm = dir_buf<R>(links, g, dm), bn = dir_buf<R>(links, g, dn);
   auto at = [&](int a, int b) {
     int e[4] = {c[0], c[1], c[2], c[3]};
@@ -1022,34 +1042,52 @@ __device__ __forceinline__ M3<double> clover_at(const Geo& g, const void* links,
     e[dn] = wrap_add(e[dn], b, g.L[dn]);
     return site_index(g, e);
   };
-  auto L = [&](const DirBuf<R>& b, uint32_t i) {
-    const M3<double> m = mconvert<double>(ld_link(b, i));
-    load_fence();
-    return m;
-  };
+  auto F = [&](const M3<R>& r) { return mconvert<double>(full(r)); };
   // full 3x3 products: links stored in FP32 are unitary only to FP32 rounding,
-  // so a row rebuilt from two others would not be the product's own
+  // so a row rebuilt from two others would not be the product's own.  The four
+  // links of a leaf are loaded together.
   M3<double> C = mzero<double>();
   M3<double> t;
-  // U_mu(x) U_nu(x+mu) U_mu^dag(x+nu) U_nu^dag(x)
-  t = mul_nn(L(bm, at(0, 0)), L(bn, at(1, 0)));
-  t = mul_nd(t, L(bm, at(0, 1)));
-  t = mul_nd(t, L(bn, at(0, 0)));
+  {
+    // U_mu(x) U_nu(x+mu) U_mu^dag(x+nu) U_nu^dag(x)
+    const M3<R> a = ld_rows(bm, at(0, 0)), b = ld_rows(bn, at(1, 0)), c_ = ld_rows(bm, at(0, 1)),
+                d = ld_rows(bn, at(0, 0));
+    load_fence();
+    t = mul_nn(F(a), F(b));
+    t = mul_nd(t, F(c_));
+    t = mul_nd(t, F(d));
+  }
+  wilson = (1.0 - t.a[0].re) + (1.0 - t.a[4].re) + (1.0 - t.a[8].re);
   maxpy(C, 0.25, t);
-  // U_nu(x) U_mu^dag(x-mu+nu) U_nu^dag(x-mu) U_mu(x-mu)
-  t = mul_nd(L(bn, at(0, 0)), L(bm, at(-1, 1)));
-  t = mul_nd(t, L(bn, at(-1, 0)));
-  t = mul_nn(t, L(bm, at(-1, 0)));
+  {
+    // U_nu(x) U_mu^dag(x-mu+nu) U_nu^dag(x-mu) U_mu(x-mu)
+    const M3<R> a = ld_rows(bn, at(0, 0)), b = ld_rows(bm, at(-1, 1)), c_ = ld_rows(bn, at(-1, 0)),
+                d = ld_rows(bm, at(-1, 0));
+    load_fence();
+    t = mul_nd(F(a), F(b));
+    t = mul_nd(t, F(c_));
+    t = mul_nn(t, F(d));
+  }
   maxpy(C, 0.25, t);
-  // U_mu^dag(x-mu) U_nu^dag(x-mu-nu) U_mu(x-mu-nu) U_nu(x-nu)
-  t = madj(mul_nn(L(bn, at(-1, -1)), L(bm, at(-1, 0))));
-  t = mul_nn(t, L(bm, at(-1, -1)));
-  t = mul_nn(t, L(bn, at(0, -1)));
+  {
+    // U_mu^dag(x-mu) U_nu^dag(x-mu-nu) U_mu(x-mu-nu) U_nu(x-nu)
+    const M3<R> a = ld_rows(bn, at(-1, -1)), b = ld_rows(bm, at(-1, 0)), c_ = ld_rows(bm, at(-1, -1)),
+                d = ld_rows(bn, at(0, -1));
+    load_fence();
+    t = madj(mul_nn(F(a), F(b)));
+    t = mul_nn(t, F(c_));
+    t = mul_nn(t, F(d));
+  }
   maxpy(C, 0.25, t);
-  // U_nu^dag(x-nu) U_mu(x-nu) U_nu(x+mu-nu) U_mu^dag(x)
-  t = mul_dn(L(bn, at(0, -1)), L(bm, at(0, -1)));
-  t = mul_nn(t, L(bn, at(1, -1)));
-  t = mul_nd(t, L(bm, at(0, 0)));
+  {
+    // U_nu^dag(x-nu) U_mu(x-nu) U_nu(x+mu-nu) U_mu^dag(x)
+    const M3<R> a = ld_rows(bn, at(0, -1)), b = ld_rows(bm, at(0, -1)), c_ = ld_rows(bn, at(1, -1)),
+                d = ld_rows(bm, at(0, 0));
+    load_fence();
+    t = mul_dn(F(a), F(b));
+    t = mul_nn(t, F(c_));
+    t = mul_nd(t, F(d));
+  }
   maxpy(C, 0.25, t);
   return C;
 }
@@ -1094,40 +1132,25 @@ static_assert(sizeof(ClovPartial) == 80, "clover partials share the measurement 
 template <typename R>
 __global__ void __launch_bounds__(256) k_clover(Geo g, const void* links, ClovPartial* __restrict__ part,
                                                 double* __restrict__ sdens, double* __restrict__ qdens) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  // sites in the order of k_measure
+  const uint32_t blk = xcd_block();
   KSum ksr = {0.0, 0.0}, kq = {0.0, 0.0}, ks = {0.0, 0.0};
-  if (t < g.V) {
-    int c[4];
-    coords_of_index(g, t, c);
+  int c[4];
+  if (chunk_site(g, blk, c)) {
     double sr = 0.0, q = 0.0, sw = 0.0;
-    // plane pairs (01, 23), (02, 13), (03, 12) with signs +, -, +
+    // plane pairs (01, 23), (02, 13), (03, 12) with signs +, -, +; together
+    // they visit all six planes once, so the Wilson density comes from the
+    // first clover leaves
 #pragma unroll 1
     for (int pr = 0; pr < 3; ++pr) {
       const int a0 = 0, a1 = pr + 1;
       const int b0 = pr == 0 ? 2 : 1, b1 = pr == 2 ? 2 : 3;
-      const M3<double> Fa = field_strength(clover_at<R>(g, links, c, g.perm[a0], g.perm[a1]));
-      const M3<double> Fb = field_strength(clover_at<R>(g, links, c, g.perm[b0], g.perm[b1]));
+      double wa, wb;
+      const M3<double> Fa = field_strength(clover_at<R>(g, links, c, g.perm[a0], g.perm[a1], wa));
+      const M3<double> Fb = field_strength(clover_at<R>(g, links, c, g.perm[b0], g.perm[b1], wb));
       sr += retr_prod(Fa, Fa) + retr_prod(Fb, Fb);
       q += (pr == 1 ? -1.0 : 1.0) * retr_prod(Fa, Fb);
-    }
-    // Wilson action density from the plaquettes at x
-#pragma unroll 1
-    for (int plane = 0; plane < 6; ++plane) {
-      const int mu = plane < 3 ? 0 : (plane < 5 ? 1 : 2);
-      const int nu = plane < 3 ? plane + 1 : (plane < 5 ? plane - 1 : 3);
-      const int dm = g.perm[mu], dn = g.perm[nu];
-      int cm[4] = {c[0], c[1], c[2], c[3]};
-      cm[dm] = wrap_add(cm[dm], 1, g.L[dm]);
-      int cn[4] = {c[0], c[1], c[2], c[3]};
-      cn[dn] = wrap_add(cn[dn], 1, g.L[dn]);
-      const DirBuf<R> bmu = dir_buf<R>(links, g, dm), bnu = dir_buf<R>(links, g, dn);
-      M3<double> P = mul_nn(mconvert<double>(ld_link(bmu, t)), mconvert<double>(ld_link(bnu, site_index(g, cm))));
-      load_fence();
-      P = mul_nd(P, mconvert<double>(ld_link(bmu, site_index(g, cn))));
-      load_fence();
-      P = mul_nd(P, mconvert<double>(ld_link(bnu, t)));
-      load_fence();
-      sw += (1.0 - P.a[0].re) + (1.0 - P.a[4].re) + (1.0 - P.a[8].re);
+      sw += wa + wb;
     }
     const double norm = 1.0 / 72.0;
     sr *= norm;
@@ -1156,7 +1179,7 @@ __global__ void __launch_bounds__(256) k_clover(Geo g, const void* links, ClovPa
       kmerge(b, KSum{w[i].q_s, w[i].q_c});
       kmerge(d, KSum{w[i].s_s, w[i].s_c});
     }
-    part[blockIdx.x] = ClovPartial{a.s, a.c, b.s, b.c, d.s, d.c, {0, 0, 0, 0}};
+    part[blk] = ClovPartial{a.s, a.c, b.s, b.c, d.s, d.c, {0, 0, 0, 0}};
   }
 }
 
