@@ -146,37 +146,13 @@ __global__ void k_gauge(Geo g, void* links, const double2* __restrict__ gauge) {
 // ------------------------------------------------------------------ staples
 
 // Staple paths as chains of link products (Eq. plaq_staples and the
-// over-improvement diagrams).  A chain multiplies a running product by one link
-// (or its adjoint) at a time, so that only Sigma, the running product, the link
-// being multiplied and the next link in flight are live.  The compiler-only
-// memory fence after every load keeps a link that several paths share from
-// being loaded once and held across the whole staple (36 VGPRs per matrix in
-// FP64): it is reloaded from cache instead, and the load of the next link can
-// still overlap the current product.
+// over-improvement diagrams).  Links are loaded as rows 0 and 1 and completed
+// (row 2 rebuilt) where a product needs them; running products keep only rows
+// 0 and 1 too (a product of SU(3) links), and chain_add rebuilds row 2 before a
+// path is added to Sigma.  The compiler-only memory fence after a group of
+// loads fixes how far ahead of their use loads are issued: without it the
+// compiler hoists every load of the staple and spills.
 __device__ __forceinline__ void load_fence() { asm volatile("" ::: "memory"); }
-
-// Chain products keep only rows 0 and 1 of the running product (it is a
-// product of SU(3) links, so row 2 follows from them); chain_end rebuilds row 2
-// before the path is added to Sigma.
-template <typename R, bool D>
-__device__ __forceinline__ void chain_step(M3<R>& run, const DirBuf<R>& b, uint32_t i) {
-  const M3<R> m = ld_link(b, i);
-  load_fence();
-  run = D ? mul2_nd(run, m) : mul2_nn(run, m);
-}
-
-template <typename R, bool D0, bool D1>
-__device__ __forceinline__ M3<R> chain_start(const DirBuf<R>& b0, uint32_t i0, const DirBuf<R>& b1,
-                                             uint32_t i1) {
-  const M3<R> x = ld_link(b0, i0);
-  load_fence();
-  const M3<R> y = ld_link(b1, i1);
-  load_fence();
-  if (!D0 && !D1) return mul2_nn(x, y);
-  if (!D0 && D1) return mul2_nd(x, y);
-  if (D0 && !D1) return mul2_dn(x, y);
-  return mul2_dd(x, y);
-}
 
 template <typename R>
 __device__ __forceinline__ void chain_add(M3<R>& S, R c, M3<R> w) {
@@ -197,7 +173,7 @@ __device__ __forceinline__ uint32_t nbi(const Geo& g, const Nb& o, int a, int b)
   return (uint32_t)((o.S + a + b) & 3) * g.V4 + (uint32_t)((int)o.j + o.dm[a + 1] + o.dn[b + 2]);
 }
 
-// Sigma contribution of one nu and one orientation.  Paths from x to x + mu
+// The staple paths of one nu and one orientation, from x to x + mu
 // (a step -d multiplies the adjoint of the link it walks back along):
 //   +nu: plaquette  +nu +mu -nu          : U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
 //        1x2        +nu +nu +mu -nu -nu  : U_nu(x) U_nu(x+nu) U_mu(x+2nu) U_nu(x+mu+nu)^dag U_nu(x+mu)^dag
@@ -205,60 +181,13 @@ __device__ __forceinline__ uint32_t nbi(const Geo& g, const Nb& o, int a, int b)
 //        2x1 middle -mu +nu +mu +mu -nu  : U_mu(x-mu)^dag U_nu(x-mu) U_mu(x-mu+nu) U_mu(x+nu) U_nu(x+mu)^dag
 //   -nu: the same paths with nu reversed.
 // Weights: (5 - 2 eps)/3 for the plaquette staple, (eps - 1)/(12 u0^2) for rectangles.
-template <typename R, bool OI, bool UP>
-__device__ __forceinline__ void staple_dir(M3<R>& S, const DirBuf<R>& bm, const DirBuf<R>& bn,
-                                           const Geo& g, const Nb& o, R cp, R cr) {
-  auto I = [&](int a, int b) { return nbi(g, o, a, b); };
-  if (UP) {
-    M3<R> w = chain_start<R, false, false>(bn, I(0, 0), bm, I(0, 1));
-    chain_step<R, true>(w, bn, I(1, 0));
-    chain_add(S, cp, w);
-    if (!OI) return;
-    w = chain_start<R, false, false>(bn, I(0, 0), bn, I(0, 1));
-    chain_step<R, false>(w, bm, I(0, 2));
-    chain_step<R, true>(w, bn, I(1, 1));
-    chain_step<R, true>(w, bn, I(1, 0));
-    chain_add(S, cr, w);
-    w = chain_start<R, false, false>(bn, I(0, 0), bm, I(0, 1));
-    chain_step<R, false>(w, bm, I(1, 1));
-    chain_step<R, true>(w, bn, I(2, 0));
-    chain_step<R, true>(w, bm, I(1, 0));
-    chain_add(S, cr, w);
-    w = chain_start<R, true, false>(bm, I(-1, 0), bn, I(-1, 0));
-    chain_step<R, false>(w, bm, I(-1, 1));
-    chain_step<R, false>(w, bm, I(0, 1));
-    chain_step<R, true>(w, bn, I(1, 0));
-    chain_add(S, cr, w);
-  } else {
-    M3<R> w = chain_start<R, true, false>(bn, I(0, -1), bm, I(0, -1));
-    chain_step<R, false>(w, bn, I(1, -1));
-    chain_add(S, cp, w);
-    if (!OI) return;
-    w = chain_start<R, true, true>(bn, I(0, -1), bn, I(0, -2));
-    chain_step<R, false>(w, bm, I(0, -2));
-    chain_step<R, false>(w, bn, I(1, -2));
-    chain_step<R, false>(w, bn, I(1, -1));
-    chain_add(S, cr, w);
-    w = chain_start<R, true, false>(bn, I(0, -1), bm, I(0, -1));
-    chain_step<R, false>(w, bm, I(1, -1));
-    chain_step<R, false>(w, bn, I(2, -1));
-    chain_step<R, true>(w, bm, I(1, 0));
-    chain_add(S, cr, w);
-    w = chain_start<R, true, true>(bm, I(-1, 0), bn, I(-1, -1));
-    chain_step<R, false>(w, bm, I(-1, -1));
-    chain_step<R, false>(w, bm, I(0, -1));
-    chain_step<R, false>(w, bn, I(1, -1));
-    chain_add(S, cr, w);
-  }
-}
-
-// The same paths with every distinct link loaded once per orientation (10
-// loads instead of 18) and the plaquette staple sharing A B with the 2x1 path
-// whose site x sits at the left; K = U_mu(x+mu) and L = U_mu(x-mu) are common to
-// all nu and loaded once by the caller.  Links are loaded as rows 0 and 1 and
-// completed per use; each load is issued two products ahead of its first use,
-// so that two links are in flight while a product runs (the fences keep the
-// compiler from hoisting more loads than that, which would spill).
+//
+// staple_dir_shared adds these paths with every distinct link loaded once per
+// orientation (10 loads instead of 18) and the plaquette staple sharing A B
+// with the 2x1 path whose site x sits at the left; K = U_mu(x+mu) and
+// L = U_mu(x-mu) are common to all nu and loaded once by the caller.  B and C
+// are completed once for their several uses.  Each load is issued two products
+// ahead of its first use, so that two links are in flight while a product runs.
 template <typename R, bool UP>
 __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm, const DirBuf<R>& bn,
                                                   const Geo& g, const Nb& o, R cp, R cr,
@@ -280,13 +209,15 @@ __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm,
   const M3<R> Gr = ld_rows(bm, I(1, sg));
   load_fence();
   w = UP ? mul2_nd(w, full(Fr)) : mul2_nn(w, full(Fr));
-  w = UP ? mul2_nd(w, full(Cr)) : mul2_nn(w, full(Cr));
+  const M3<R> Cf = full(Cr);
+  w = UP ? mul2_nd(w, Cf) : mul2_nn(w, Cf);
   chain_add(S, cr, w);
   // plaquette A B C^dag and 2x1 left A B G H^dag K^dag share T = A B
   const M3<R> Hr = ld_rows(bn, I(2, UP ? 0 : -1));
   load_fence();
-  M3<R> T = UP ? mul2_nn(Ar, full(Br)) : mul2_dn(full(Ar), full(Br));
-  chain_add(S, cp, UP ? mul2_nd(T, full(Cr)) : mul2_nn(T, full(Cr)));
+  const M3<R> Bf = full(Br);
+  M3<R> T = UP ? mul2_nn(Ar, Bf) : mul2_dn(full(Ar), Bf);
+  chain_add(S, cp, UP ? mul2_nd(T, Cf) : mul2_nn(T, Cf));
   const M3<R> Mr = ld_rows(bn, I(-1, UP ? 0 : -1));
   load_fence();
   T = mul2_nn(T, full(Gr));
@@ -297,8 +228,8 @@ __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm,
   // 2x1 middle: L^dag M N B C^dag
   w = UP ? mul2_dn(full(L), full(Mr)) : mul2_dd(full(L), full(Mr));
   w = mul2_nn(w, full(Nr));
-  w = mul2_nn(w, full(Br));
-  w = UP ? mul2_nd(w, full(Cr)) : mul2_nn(w, full(Cr));
+  w = mul2_nn(w, Bf);
+  w = UP ? mul2_nd(w, Cf) : mul2_nn(w, Cf);
   chain_add(S, cr, w);
 }
 
@@ -558,8 +489,19 @@ __device__ __forceinline__ M3<R> staple_sum(const Geo& g, const void* src, const
       staple_dir_shared<R, true>(S, bm, bn, g, o, cp, cr, K, Lm);
       staple_dir_shared<R, false>(S, bm, bn, g, o, cp, cr, K, Lm);
     } else {
-      staple_dir<R, OI, true>(S, bm, bn, g, o, cp, cr);
-      staple_dir<R, OI, false>(S, bm, bn, g, o, cp, cr);
+      // the six links of the two plaquette staples, loaded together:
+      // U_nu(x) U_mu(x+nu) U_nu^dag(x+mu) and U_nu^dag(x-nu) U_mu(x-nu) U_nu(x+mu-nu)
+      const M3<R> Au = ld_rows(bn, nbi(g, o, 0, 0)), Bu = ld_rows(bm, nbi(g, o, 0, 1)),
+                  Cu = ld_rows(bn, nbi(g, o, 1, 0));
+      const M3<R> Ad = ld_rows(bn, nbi(g, o, 0, -1)), Bd = ld_rows(bm, nbi(g, o, 0, -1)),
+                  Cd = ld_rows(bn, nbi(g, o, 1, -1));
+      load_fence();
+      M3<R> w = mul2_nn(Au, full(Bu));
+      w = mul2_nd(w, full(Cu));
+      chain_add(S, cp, w);
+      w = mul2_dn(full(Ad), full(Bd));
+      w = mul2_nn(w, full(Cd));
+      chain_add(S, cp, w);
     }
   }
   return S;
