@@ -240,32 +240,36 @@ struct Geo {
   uint32_t cst[4]; // canonical-index stride of internal axis d
   int perm[4];     // internal axis of user axis mu
   int uperm[4];    // user axis of internal axis d
-  int T1, T2;      // traversal tile: rows of axes 1 and 2 swept together through axis 3
+  int T1, T2, T3;  // traversal tiles: rows of axis 1 (T1) with rows of axis 2 (T2) or axis 3 (T3)
 };
 
 // Axes 1..3 of the r-th row (x1, x2, x3) in traversal order (a row is the
 // run of x0 positions one j-range covers).  The lattice is cut into tiles of
-// T1 x T2 rows of axes 1 and 2, and each tile is swept through the whole of
-// axis 3 before the next, so that the neighbours along axes 2 and 3 of what a
-// pass is updating were read a short time before.  T1 = L1, T2 = L2 is plain
-// row order.  With half = 1 the row index counts axis-1 pairs (x1 = 2 y + p):
-// the caller passes y back in c[1].
+// T1 rows of axis 1 by T2 rows of axis 2, and each tile is swept through the
+// whole of axis 3 before the next (SW = 3), so that the neighbours along the
+// tile axes and the sweep axis of what a pass is updating were read a short
+// time before.  With SW = 2 the roles of axes 2 and 3 swap (tiles T1 x T3,
+// swept along axis 2): a pass of direction 3 reaches further along its own
+// axis, which is then a tile axis.  With half = 1 the row index counts axis-1
+// pairs (x1 = 2 y + p): the caller passes y back in c[1].
+template <int SW = 3>
 __device__ __forceinline__ void tile_rows(const Geo& g, uint32_t r, int c[4], int half) {
+  constexpr int B = SW == 3 ? 2 : 3;
   const uint32_t L1 = (uint32_t)(g.L[1] >> half), T1 = (uint32_t)(g.T1 >> half);
-  const uint32_t T2 = (uint32_t)g.T2, L3 = (uint32_t)g.L[3];
-  const uint32_t inner = T1 * T2 * L3;
+  const uint32_t T2 = (uint32_t)(SW == 3 ? g.T2 : g.T3), LS = (uint32_t)g.L[SW];
+  const uint32_t inner = T1 * T2 * LS;
   const uint32_t tile = r / inner;
   uint32_t q = r - tile * inner;
   const uint32_t a = q % T1;
   q /= T1;
   const uint32_t b = q % T2;
-  const uint32_t x3 = q / T2;
+  const uint32_t xs = q / T2;
   const uint32_t n1 = L1 / T1;
   const uint32_t t2 = tile / n1;
   const uint32_t t1 = tile - t2 * n1;
   c[1] = (int)(t1 * T1 + a);
-  c[2] = (int)(t2 * T2 + b);
-  c[3] = (int)x3;
+  c[B] = (int)(t2 * T2 + b);
+  c[SW] = (int)xs;
 }
 
 __device__ __forceinline__ uint32_t site_index(const Geo& g, const int c[4]) {

@@ -75,7 +75,7 @@ inline Geo make_geo(const int32_t dims[4]) {
   g.jst[2] = (uint32_t)g.Xq * (uint32_t)g.L[1];
   g.jst[3] = (uint32_t)g.Xq * (uint32_t)g.L[1] * (uint32_t)g.L[2];
   // traversal tiles (see tile_rows): the largest even divisor of L1 up to 16
-  // and the largest divisor of L2 up to 8, the best measured on 48^3x96
+  // and the largest divisors of L2 and L3 up to 8, the best measured on 48^3x96
   g.T1 = 2;
   for (int t = 16; t >= 2; t -= 2)
     if (g.L[1] % t == 0) {
@@ -86,6 +86,12 @@ inline Geo make_geo(const int32_t dims[4]) {
   for (int t = 8; t >= 1; --t)
     if (g.L[2] % t == 0) {
       g.T2 = t;
+      break;
+    }
+  g.T3 = 1;
+  for (int t = 8; t >= 1; --t)
+    if (g.L[3] % t == 0) {
+      g.T3 = t;
       break;
     }
   return g;

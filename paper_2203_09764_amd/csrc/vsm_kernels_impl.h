@@ -514,11 +514,20 @@ __device__ __forceinline__ M3<R> staple_sum(const Geo& g, const void* src, const
 //            (c - x_mu) mod 4, so thread t takes j = t;
 //   mu == 0: only rows with x1 + x2 + x3 of the parity of c take part, each with
 //            the two residues x0 mod 4 = h, h + 2, h = ((c - x1 - x2 - x3) mod 4) / 2.
-template <int MU>
+// The sweep axis of the traversal (tile_rows): never MU itself, whose
+// neighbours the staples reach furthest; for the FP32 form (twice the blocks in
+// flight) axis 2 otherwise, for FP64 axis 3 (both chosen with a model of the L2
+// and confirmed by timing on 48^3x96).
+template <typename R, int MU>
+constexpr int sweep_axis() {
+  return MU == 3 ? 2 : (MU == 2 ? 3 : (sizeof(R) == 4 ? 2 : 3));
+}
+
+template <int MU, int SW>
 __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t, int c[4]) {
   if (MU != 0) {
     const uint32_t xi = t % (uint32_t)g.Xq;
-    tile_rows(g, t / (uint32_t)g.Xq, c, 0);
+    tile_rows<SW>(g, t / (uint32_t)g.Xq, c, 0);
     const int s = (colour - c[MU]) & 3;
     c[0] = (int)(4 * xi) + ((s - c[1] - c[2] - c[3]) & 3);
   } else {
@@ -527,7 +536,7 @@ __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t
     const uint32_t rem = t - k * two;
     const uint32_t which = rem / (uint32_t)g.Xq;
     const uint32_t xi = rem - which * (uint32_t)g.Xq;
-    tile_rows(g, k, c, 1);
+    tile_rows<SW>(g, k, c, 1);
     c[1] = 2 * c[1] + ((colour - c[2] - c[3]) & 1);
     const int S = c[1] + c[2] + c[3];
     const int h = ((colour - S) & 3) >> 1;
@@ -553,7 +562,7 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
     if (jacobi)
       coords_of_index(g, t, c);
     else
-      subset_site<MU>(g, colour, t, c);
+      subset_site<MU, sweep_axis<R, MU>()>(g, colour, t, c);
   }
   bool rej = false;
   if (active) {
