@@ -544,6 +544,32 @@ __device__ __forceinline__ void subset_site(const Geo& g, int colour, uint32_t t
   }
 }
 
+// XCD-aware block order: consecutive hardware blocks go round-robin to the 8
+// XCDs; this gives each XCD one contiguous range of the lattice (when the grid
+// is a multiple of 8 blocks), so that neighbouring blocks share an L2.
+__device__ __forceinline__ uint32_t xcd_block() {
+  const uint32_t b = blockIdx.x, nb = gridDim.x;
+  return (nb & 7u) == 0u ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+}
+
+// Site of thread t of a kernel that visits every site (measurement, Jacobi
+// smearing, flow), in blocks of 256.  Block t / 256 takes a chunk of 64
+// positions j (rows of internal axis 0 in the tile order of the update) and
+// its four waves take the four sublattices of that chunk: a wave's loads of a
+// link entry are one contiguous run, and the neighbour x + mu of a site (the
+// next sublattice) is read by another wave of the same block.  Returns false
+// for threads past the end of the lattice.
+__device__ __forceinline__ bool chunk_site(const Geo& g, uint32_t t, int c[4]) {
+  const uint32_t tj = (t >> 8) * 64u + (t & 63u);
+  if (tj >= g.V4) return false;
+  const uint32_t s = (t >> 6) & 3u;
+  const uint32_t row = tj / (uint32_t)g.Xq;
+  const uint32_t xi = tj - row * (uint32_t)g.Xq;
+  tile_rows(g, row, c, 0);
+  c[0] = (int)(4u * xi) + (int)((s - (uint32_t)(c[1] + c[2] + c[3])) & 3u);
+  return true;
+}
+
 // One link update of direction MU for thread t: jacobi = 0, the t-th link of
 // annealing subset `colour`, in place (src == dst); jacobi = 1, link t of
 // direction MU from src into dst (smearing).  UPD = 0 stout, 1 MaxReTr.  With
@@ -560,7 +586,7 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
   int c[4] = {0, 0, 0, 0};
   if (active) {
     if (jacobi)
-      coords_of_index(g, t, c);
+      chunk_site(g, t, c);
     else
       subset_site<MU, sweep_axis<R, MU>()>(g, colour, t, c);
   }
@@ -611,31 +637,6 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
 
 // One update step for direction MU over the whole lattice (see update_one);
 // rejections are counted per wave into *rejected.
-// XCD-aware block order: consecutive hardware blocks go round-robin to the 8
-// XCDs; this gives each XCD one contiguous range of the lattice (when the grid
-// is a multiple of 8 blocks), so that neighbouring blocks share an L2.
-__device__ __forceinline__ uint32_t xcd_block() {
-  const uint32_t b = blockIdx.x, nb = gridDim.x;
-  return (nb & 7u) == 0u ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
-}
-
-// Site of a thread of the measurement kernels (blocks of 256).  Block b takes
-// a chunk of 64 positions j (rows of internal axis 0 in the tile order of the
-// update) and its four waves take the four sublattices of that chunk: a wave's
-// loads of a link entry are one contiguous run, and the neighbour x + mu of a
-// site (the next sublattice) is read by another wave of the same block.
-// Returns false for threads past the end of the lattice.
-__device__ __forceinline__ bool chunk_site(const Geo& g, uint32_t b, int c[4]) {
-  const uint32_t tj = b * 64u + (threadIdx.x & 63u);
-  if (tj >= g.V4) return false;
-  const uint32_t s = (threadIdx.x >> 6) & 3u;
-  const uint32_t row = tj / (uint32_t)g.Xq;
-  const uint32_t xi = tj - row * (uint32_t)g.Xq;
-  tile_rows(g, row, c, 0);
-  c[0] = (int)(4u * xi) + (int)((s - (uint32_t)(c[1] + c[2] + c[3])) & 3u);
-  return true;
-}
-
 template <typename R, int MU, bool OI, int UPD>
 __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* dst,
                                                 const int8_t* __restrict__ z3,
@@ -709,10 +710,9 @@ __global__ void __launch_bounds__(256) k_update_batch(const ServeJob* __restrict
 template <typename R, int MU, bool OI>
 __global__ void __launch_bounds__(256) k_flow(Geo g, const void* src, void* dst, double* __restrict__ acc,
                                               int stage, double eps, double cp, double cr) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.V) return;
   int c[4];
-  coords_of_index(g, t, c);
+  if (!chunk_site(g, xcd_block() * 256u + threadIdx.x, c)) return;
+  const uint32_t t = site_index(g, c);
   const M3<R> S = staple_sum<R, MU, OI>(g, src, c, t, (R)cp, (R)cr);
   const M3<R> U = ld_link(dir_buf<R>(src, g, MU), t);
   const M3<R> Hz = stout_h(S, U, eps);
@@ -796,7 +796,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
   double maxu2 = 0.0;  // largest |(U^dag U - 1)_ij|^2; its root is taken once per thread
   long long mism = 0, undef = 0, nonfin = 0;
   int c[4];
-  if (chunk_site(g, blk, c)) {
+  if (chunk_site(g, blk * 256u + threadIdx.x, c)) {
     const uint32_t x = site_index(g, c);
     const uint32_t s = canonical_index(g, c);
     // original charges of the four links at x (user directions), one byte each;
@@ -1087,7 +1087,7 @@ __global__ void __launch_bounds__(256) k_clover(Geo g, const void* links, ClovPa
   const uint32_t blk = xcd_block();
   KSum ksr = {0.0, 0.0}, kq = {0.0, 0.0}, ks = {0.0, 0.0};
   int c[4];
-  if (chunk_site(g, blk, c)) {
+  if (chunk_site(g, blk * 256u + threadIdx.x, c)) {
     double sr = 0.0, q = 0.0, sw = 0.0;
     // plane pairs (01, 23), (02, 13), (03, 12) with signs +, -, +; together
     // they visit all six planes once, so the Wilson density comes from the
