@@ -4,9 +4,10 @@ by one.
 
 * Centrifuge preconditioning (Sec. IV): the integer staple charges m of every
   link bit-exact; sampled links within 1e-15.
-* One annealing subset pass (Sec. III.A, V, VI) of over-improved stout with
+* Annealing subset passes (Sec. III.A, V, VI) of over-improved stout with
   vortex preservation, from the preconditioned field and again from the field
-  after two more GPU sweeps: 512 sampled updated links against the oracle's
+  after two more GPU sweeps, in directions that use both sweep axes of the
+  traversal: 512 sampled updated links against the oracle's
   update of the same input within 1e-12 (FP64) and, for the FP32-bulk form,
   within 2e-6; sampled links outside the subset unchanged, bit for bit.
 * Properties that hold at any size: no vortex lost, no non-finite link.
@@ -85,10 +86,13 @@ def test_full_size_fp64_passes_sampled(cfg):
     V = fieldgen.volume(dims)
     mus0, sites0 = rng.integers(0, 4, N_SAMPLES), rng.integers(0, V, N_SAMPLES)
     assert np.abs(_gather(f, mus0, sites0) - U[mus0, sites0]).max() < 1e-15
-    for step, (mu, colour) in enumerate([(0, 0), (3, 3)]):
+    # user directions 0, 2, 3: internal directions 1, 3, 0 at both sizes, so
+    # both sweep axes of the traversal are exercised
+    for step, (mu, colour) in enumerate([(0, 0), (3, 3), (2, 1)]):
         if step == 1:
             # a later, non-diagonal field: two more sweeps on the GPU, read back
             api.smooth(f, 2, rho, eps, order="annealed", vp=True)
+        if step >= 1:
             del U
             U = api.get_links(f).cpu().numpy()
         print(f"[{cfg}] pass mu={mu} colour={colour}", flush=True)
@@ -117,13 +121,17 @@ def test_full_size_fp32_bulk_first_pass_sampled():
     f.set_charges(n)
     api.precondition(f, pairs, c["omega"])
     U = ora.centrifuge(dims, n, pairs, c["omega"])
-    mu, colour = 1, 2
-    sites = _subset_sample(dims, mu, colour, N_SAMPLES, 30)
-    want, _ = ora.update_links(dims, U, n, np.full(N_SAMPLES, mu), sites, rho=rho, eps=eps, vp=True)
-    api.anneal_pass(f, mu, colour, rho, eps, vp=True)
-    got = _gather(f, np.full(N_SAMPLES, mu), sites)
-    err = np.abs(got - want).max()
-    print(f"[c4 fp32_bulk] pass mu={mu} colour={colour}: max link error {err:.2e}", flush=True)
-    assert err < 2e-6
+    # user directions 1 and 3: internal 2 (sweep axis 3) and 0 (sweep axis 2)
+    for step, (mu, colour) in enumerate([(1, 2), (3, 1)]):
+        if step == 1:
+            del U
+            U = api.get_links(f).cpu().numpy()
+        sites = _subset_sample(dims, mu, colour, N_SAMPLES, 30 + step)
+        want, _ = ora.update_links(dims, U, n, np.full(N_SAMPLES, mu), sites, rho=rho, eps=eps, vp=True)
+        api.anneal_pass(f, mu, colour, rho, eps, vp=True)
+        got = _gather(f, np.full(N_SAMPLES, mu), sites)
+        err = np.abs(got - want).max()
+        print(f"[c4 fp32_bulk] pass mu={mu} colour={colour}: max link error {err:.2e}", flush=True)
+        assert err < 2e-6
     rec = api.stats_to_numpy(api.measure(f), 1)[0]
     assert rec.flux_mismatch == 0 and rec.nonfinite == 0
