@@ -662,7 +662,10 @@ __device__ __forceinline__ bool batch_one(const ServeJob& J, int colour, uint32_
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_update_batch(const ServeJob* __restrict__ jobs, BatchStep st) {
-  const uint32_t b = blockIdx.x;
+  // blocks in XCD ranges, so that a job's neighbouring blocks share an L2; the
+  // grid is padded to a multiple of 8 and the padding blocks fall past the end
+  // of the last job (t >= its thread count: nothing to do)
+  const uint32_t b = xcd_block();
   uint32_t fb = st.first_block[0], slot = st.slot[0];
   int mu = st.mu[0], colour = st.colour[0];
 #pragma unroll
@@ -1248,7 +1251,8 @@ template <typename R>
 void launch_update_batch_t(const ServeJob* jobs, const BatchStep& step, uint32_t nblocks, hipStream_t st) {
   // the same cap on resident blocks per CU as for single-field passes
   const unsigned lds = sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u;
-  hipLaunchKernelGGL(k_update_batch<R>, dim3(nblocks), dim3(256), lds, st, jobs, step);
+  const uint32_t nb8 = (nblocks + 7u) & ~7u;
+  hipLaunchKernelGGL(k_update_batch<R>, dim3(nb8), dim3(256), lds, st, jobs, step);
 }
 
 template <typename R, int MU>
