@@ -265,7 +265,8 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=50.0, help="mean arrivals per second")
     ap.add_argument("--serving-slots", type=int, default=64, help="jobs resident at once")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run 5 plain device copies of MIB mebibytes (counter calibration)")
+                    help="only run 5 plain device copies of MIB mebibytes (counter calibration), then 5 "
+                         "reads, and print their rates")
     args = ap.parse_args()
     if args.copy_calibration > 0:
         import torch
@@ -275,10 +276,21 @@ def main():
         b = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
         a.fill_(1)
         torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
         for _ in range(5):
             b.copy_(a)
+        e1.record(stream)
+        # a plain streaming read of the same bytes, for the practical HBM read rate
+        for _ in range(5):
+            a.view(torch.float64).sum()
+        e2.record(stream)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": nb, "copies": 5}))
+        copy_ms, read_ms = e0.elapsed_time(e1) / 5, e1.elapsed_time(e2) / 5
+        print(json.dumps({"copy_calibration_bytes": nb, "copies": 5,
+                          "copy_gb_per_s": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1),
+                          "read_gb_per_s": round(nb / (read_ms * 1e-3) / 1e9, 1)}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

@@ -571,8 +571,9 @@ __device__ __forceinline__ bool chunk_site(const Geo& g, uint32_t t, int c[4]) {
 }
 
 // One link update of direction MU for thread t: jacobi = 0, the t-th link of
-// annealing subset `colour`, in place (src == dst); jacobi = 1, link t of
-// direction MU from src into dst (smearing).  UPD = 0 stout, 1 MaxReTr.  With
+// annealing subset `colour` (subset_site), in place (src == dst); jacobi = 1,
+// the link of direction MU at chunk_site(t), from src into dst (smearing).
+// UPD = 0 stout, 1 MaxReTr, 2 APE with unit circle projection.  With
 // vp, a candidate is kept only if its centre sector (after undoing the gauge
 // transform, when one is given) equals the original charge (z3, canonical
 // layout: one byte per update, not worth a relayout).  Returns whether a
