@@ -1,6 +1,8 @@
 """GPU parity at the full workload sizes (32^3 x 64 and 48^3 x 96), in the launch
-configuration the benchmark times, on sampled outputs the oracle computes one
-by one.
+configuration the benchmark times, and at the largest lattices the C ABI
+accepts (48^3 x 200 in FP64, 48^3 x 404 in FP32-bulk: one direction's six
+entry arrays just under 2^31 bytes, where the 32-bit buffer offsets end), on
+sampled outputs the oracle computes one by one.
 
 * Centrifuge preconditioning (Sec. IV): the integer staple charges m of every
   link bit-exact; sampled links within 1e-15.
@@ -18,11 +20,29 @@ import torch
 
 import fieldgen
 import oracle as ora
-from paper_2203_09764_amd import api
+from paper_2203_09764_amd import _lib, api
 
 pytestmark = pytest.mark.gpu
 
 N_SAMPLES = 512
+
+# the largest lattices of the 48^3 x 96 recipe's cross-section that the C ABI
+# accepts in each form (the next multiple of 4 along t is refused)
+MAX_DIMS = {"fp64": (48, 48, 48, 200), "fp32_bulk": (48, 48, 48, 404)}
+
+
+def _recipe(cfg):
+    """Dims and parameters: a named workload, or the 48^3 x 96 recipe at the
+    largest accepted size of a form ("max_fp64", "max_fp32_bulk")."""
+    if cfg.startswith("max_"):
+        prec = cfg[4:]
+        dims = MAX_DIMS[prec]
+        code = _lib.FP64 if prec == "fp64" else _lib.FP32_BULK
+        assert _lib.lib().vsm_check_dims(_lib.dims_arg(dims), _lib.ANNEALED, code) == 0
+        bigger = dims[:3] + (dims[3] + 4,)
+        assert _lib.lib().vsm_check_dims(_lib.dims_arg(bigger), _lib.ANNEALED, code) == _lib.E_DIMS
+        return dict(fieldgen.CONFIGS["c4"], dims=dims)
+    return fieldgen.CONFIGS[cfg]
 
 
 def _coords(dims, s):
@@ -69,9 +89,9 @@ def _gather(f, mus, sites):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("cfg", ["c2", "c4"])
+@pytest.mark.parametrize("cfg", ["c2", "c4", "max_fp64"])
 def test_full_size_fp64_passes_sampled(cfg):
-    c = fieldgen.CONFIGS[cfg]
+    c = _recipe(cfg)
     dims, rho, eps = c["dims"], c["rho"], c["eps"]
     print(f"[{cfg}] {dims}: generating the field", flush=True)
     n = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
@@ -112,8 +132,9 @@ def test_full_size_fp64_passes_sampled(cfg):
 
 
 @pytest.mark.timeout(900)
-def test_full_size_fp32_bulk_first_pass_sampled():
-    c = fieldgen.CONFIGS["c4"]
+@pytest.mark.parametrize("cfg", ["c4", "max_fp32_bulk"])
+def test_full_size_fp32_bulk_first_pass_sampled(cfg):
+    c = _recipe(cfg)
     dims, rho, eps = c["dims"], c["rho"], c["eps"]
     n = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
     pairs = fieldgen.centrifuge_pairs(dims, c["pair_seed"])
@@ -131,7 +152,7 @@ def test_full_size_fp32_bulk_first_pass_sampled():
         api.anneal_pass(f, mu, colour, rho, eps, vp=True)
         got = _gather(f, np.full(N_SAMPLES, mu), sites)
         err = np.abs(got - want).max()
-        print(f"[c4 fp32_bulk] pass mu={mu} colour={colour}: max link error {err:.2e}", flush=True)
+        print(f"[{cfg} fp32_bulk] pass mu={mu} colour={colour}: max link error {err:.2e}", flush=True)
         assert err < 2e-6
     rec = api.stats_to_numpy(api.measure(f), 1)[0]
     assert rec.flux_mismatch == 0 and rec.nonfinite == 0

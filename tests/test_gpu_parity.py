@@ -343,3 +343,20 @@ def test_ape_maps_a_vortex_field_to_centre_elements(precision, tol):
         th = np.angle(np.trace(Vb) / 3)
         r = (th + np.pi / 3) % (2 * np.pi / 3)  # 0 on a boundary
         assert min(r, 2 * np.pi / 3 - r) < 1e-9, (mu, s, th)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_zero_sweeps_leave_the_field_unchanged(precision):
+    """The empty run (n_sweeps = 0) is a valid call in both orders and every
+    update, and changes no link."""
+    dims = (8, 8, 8, 8)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 5)
+    f = _field(dims, precision)
+    f.set_charges(n)
+    api.precondition(f, fieldgen.centrifuge_pairs(dims, 6), 0.02)
+    before = api.get_links(f).clone()
+    for order in ("annealed", "jacobi"):
+        for update in ("stout", "maxretr", "ape"):
+            api.smooth(f, 0, 0.1, -0.25, order=order, update=update, vp=True, alpha=0.7)
+    torch.cuda.synchronize()
+    assert torch.equal(api.get_links(f), before)
