@@ -267,9 +267,19 @@ def cpu_baseline(dims, n, pairs, threads):
         dt += time.perf_counter() - t
         done += V // 4
         k += 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=done / dt, unit="link-updates/s", cores=int(used), kind="oracle",
                 sample=f"the first {k} annealing subset passes of the first sweep of the same "
-                       f"preconditioned field: {done} link updates in {dt:.1f} s")
+                       f"preconditioned field: {done} link updates in {dt:.1f} s",
+                cpu_model=model, host_cpus=os.cpu_count())
 
 
 def main():
