@@ -7,9 +7,18 @@
 //   k_centrifuge              : centrifuge preconditioning (Sec. IV)
 //   k_gauge                   : U -> G(x) U G^dagger(x + mu) (Sec. V.C)
 //   k_update<R, MU, OI, UPD>  : one annealing subset or one smearing step of
-//                               stout (Eq. stout) or MaxReTr (Sec. III) updates
-//                               with the vortex-preserving test (Sec. VI)
+//                               stout (Eq. stout), MaxReTr (Sec. III) or APE with
+//                               unit circle projection (Sec. III) updates, with the
+//                               vortex-preserving test (Sec. VI)
+//   k_update_batch            : one serving step: a subset pass of every resident job
+//   k_flow                    : one Euler or Runge-Kutta stage of the Wilson flow (Sec. II.B)
 //   k_measure / k_finalize    : plaquette, Wilson action, vortex flux (Sec. I, V.A)
+//   k_clover / k_clover_finalize : clover F, reconstructed action, topological charge (Sec. V)
+//
+// Site orders: subset passes take their sites by subset_site (rows in tiles,
+// swept along an axis other than the pass direction); kernels that visit every
+// site take them by chunk_site (one sublattice per wave, four per block).  Both
+// hand blocks to the XCDs in contiguous ranges (xcd_block).
 #pragma once
 
 #include "vsm_device.h"
