@@ -307,6 +307,8 @@ def main():
         a = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
         b = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
         a.fill_(1)
+        b.copy_(a)  # warm-up: the first copy and the first sum load their kernels
+        a.view(torch.float64).sum()
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
