@@ -16,6 +16,7 @@ from tests import _loops
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 SMALL = (4, 4, 4, 4)
+TINY = (2, 2, 2, 2)  # every wrap-around as short as it can be
 
 
 def _rows(name):
@@ -215,14 +216,16 @@ def test_centrifuge_preservation_bound(ora):
 # --------------------------------------------------------- staples and Q
 
 
-@pytest.mark.parametrize("eps", [1.0, -0.25])
-def test_staple_is_action_gradient(ora, eps):
+@pytest.mark.parametrize("dims,eps", [(SMALL, 1.0), (SMALL, -0.25), (TINY, 1.0), (TINY, -0.25)])
+def test_staple_is_action_gradient(ora, dims, eps):
     """Sec. II.B: the generator of the Wilson flow is the gradient of the action,
     d/ds A(e^{s T^a} U)|_0 for the loop-sum action A = sum c_p Re Tr P + sum c_r Re Tr R
     (Eq. over-improvement weights).  sum_a T^a dA_a equals half the traceless
     anti-Hermitian part of Omega = Sigma U^dagger (Eq. generator).  Brute force by
-    central differences on a Haar-random 4^4 field."""
-    dims = SMALL
+    central differences on Haar-random 4^4 and 2^4 fields.  On 2^4 a 1x2
+    rectangle runs through the updated link twice (once each way); the staple
+    sum holds one path per occurrence, which is the product rule, so it is
+    still the gradient."""
     U = _haar_field(dims, 21)
     T = _loops.gell_mann_generators()
     h = 1e-5
@@ -243,14 +246,16 @@ def test_staple_is_action_gradient(ora, eps):
         np.testing.assert_allclose(grad, 0.5 * Q, atol=2e-8)
 
 
-def test_staple_gauge_covariance(ora):
-    """Sec. II.A: Sigma -> G(x) Sigma G^dagger(x + mu) under a gauge transform."""
-    dims = SMALL
+@pytest.mark.parametrize("dims", [SMALL, TINY])
+def test_staple_gauge_covariance(ora, dims):
+    """Sec. II.A: Sigma -> G(x) Sigma G^dagger(x + mu) under a gauge transform,
+    also on 2^4 where x + 2 nu = x."""
     U = _haar_field(dims, 31)
-    G = fieldgen.haar_su3(fieldgen.volume(dims), 32)
+    V = fieldgen.volume(dims)
+    G = fieldgen.haar_su3(V, 32)
     UG = ora.gauge_transform(dims, U, G)
     for eps in (1.0, -0.25):
-        for mu, s in ((0, 0), (3, 77), (1, 200)):
+        for mu, s in ((0, 0), (3, 77 % V), (1, 200 % V)):
             a = ora.staple(dims, UG, mu, s, eps=eps)
             sp = fieldgen.neighbour(dims, mu, 1)[s]
             b = G[s] @ ora.staple(dims, U, mu, s, eps=eps) @ G[sp].conj().T
@@ -610,11 +615,11 @@ def test_cooling_field_sweep_stays_unitary(ora):
 # ------------------------------------------------------------- measurement
 
 
-def test_measure_normalisation_random_field(ora):
+@pytest.mark.parametrize("dims", [SMALL, TINY])
+def test_measure_normalisation_random_field(ora, dims):
     """Sec. V.A: S(x) with n_c = 3, n_d = 4; the mean over the lattice equals
     (1/2)(1 - <P>) because Re Tr[1 - P] = 3 - Re Tr P.  Checked against the
-    independent numpy plaquettes."""
-    dims = SMALL
+    independent numpy plaquettes, also by brute force on 2^4."""
     U = _haar_field(dims, 201)
     n = fieldgen.z3_vortex_charges(dims, 0.1, 202)
     st = ora.measure(dims, U, n)
@@ -624,7 +629,7 @@ def test_measure_normalisation_random_field(ora):
     assert abs(st.action - 0.5 * (1 - st.plaq)) < 1e-14
     assert st.max_unitarity < 1e-14
     W = U.copy()
-    W[2, 17, 1, 1] = np.nan
+    W[2, 17 % V, 1, 1] = np.nan
     assert ora.measure(dims, W, n).nonfinite == 1
 
 
