@@ -1,0 +1,67 @@
+"""Write the per-sweep fixture of the 32^3 x 64 workload with the FP64 oracle.
+
+Runs only oracle/ (and the seeded input generator): centrifuge preconditioning
+(omega = 0.02) of the Z(3) vortex field (p = 0.1, seeds 1002/2002), then the
+first 100 of the workload's annealed over-improved stout sweeps (rho = 0.06,
+eps = -0.25, u0 = 1) with vortex preservation.  Records plaquette, action and
+rejections after every sweep, and 64 sampled links after sweeps 1 and 2 (before
+the smoothing map has amplified rounding differences; the 16^3 x 32 fixture
+measures that amplification).
+Usage: python tests/golden/make_oracle_golden_c2.py   (about 40 minutes on 8 threads)
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import fieldgen  # noqa: E402
+import oracle  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle_first100.txt")
+N_SWEEPS = 100
+LINK_SWEEPS = (1, 2)
+N_SAMPLES = 64
+
+
+def main():
+    c = fieldgen.CONFIGS["c2"]
+    dims = c["dims"]
+    n = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
+    pairs = fieldgen.centrifuge_pairs(dims, c["pair_seed"])
+    U = oracle.centrifuge(dims, n, pairs, c["omega"])
+    V = fieldgen.volume(dims)
+    rng = np.random.default_rng(778)
+    stats, links, done = [], [], 0
+    t = time.time()
+    for k in LINK_SWEEPS + (N_SWEEPS,):
+        stats.extend(oracle.smooth(dims, U, n, k - done, order="annealed", rho=c["rho"], eps=c["eps"],
+                                   vp=True, measure_every=1))
+        done = k
+        if k in LINK_SWEEPS:
+            mus = rng.integers(0, 4, size=N_SAMPLES)
+            sites = rng.integers(0, V, size=N_SAMPLES)
+            links.extend((k, int(mu), int(s), U[mu, s].copy()) for mu, s in zip(mus, sites))
+        print(f"sweep {k}: {time.time() - t:.0f} s", flush=True)
+    dt = time.time() - t
+    with open(OUT, "w") as f:
+        f.write("# FP64 oracle, 32^3x64 workload: Z(3) vortex field p=0.1 (seeds 1002/2002),\n")
+        f.write("# centrifuge omega=0.02, the first 100 annealed over-improved stout sweeps\n")
+        f.write("# rho=0.06 eps=-0.25 u0=1 with vortex preservation (Sec. IV-VI).\n")
+        f.write("# Written by tests/golden/make_oracle_golden_c2.py (oracle only); %.0f s on %d threads.\n"
+                % (dt, oracle.set_threads(0)))
+        f.write("# section sweeps: S sweep plaq action rejected flux_mismatch\n")
+        for i, r in enumerate(stats):
+            f.write("S %d %.17e %.17e %d %d\n" % (i + 1, r.plaq, r.action, r.rejected, r.flux_mismatch))
+        f.write("# section links: L sweep mu site then 9 complex entries re im (row-major)\n")
+        for k, mu, s, u in links:
+            vals = " ".join("%.17e %.17e" % (z.real, z.imag) for z in u.reshape(-1))
+            f.write("L %d %d %d %s\n" % (k, mu, s, vals))
+    print(f"wrote {OUT}: {dt:.0f} s")
+
+
+if __name__ == "__main__":
+    main()

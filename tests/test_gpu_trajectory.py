@@ -17,6 +17,11 @@ test and the flow near vortex cores amplify rounding differences, so after
 many sweeps two correct FP64 implementations differ by that much).  The
 FP32-bulk form is held to stated bounds on the action and link errors, with no
 vortex lost.
+
+The first 100 sweeps of the 32^3 x 64 workload (seeds 1002/2002, same recipe)
+are held to the same FP64 bars against tests/golden/c2_oracle_first100.txt
+(written by tests/golden/make_oracle_golden_c2.py), and the FP32-bulk form's
+per-sweep action error against the FP64 oracle is stated and bounded.
 """
 import os
 
@@ -121,3 +126,89 @@ def test_fp32_bulk_trajectory_error_bound():
     assert np.all(rec.flux_mismatch == 0) and np.all(rec.nonfinite == 0)
     assert all(e < 1e-5 for k, e in errs.items() if k <= 10)
     assert rel.max() < 2e-3
+
+
+# ---------------------------------------------------------------- 32^3 x 64
+
+C2_FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle_first100.txt")
+
+
+def _load_c2():
+    sweeps, links = [], {}
+    with open(C2_FIXTURE) as f:
+        for line in f:
+            p = line.split()
+            if not p or p[0].startswith("#"):
+                continue
+            if p[0] == "S":
+                sweeps.append((int(p[1]), float(p[2]), float(p[3]), int(p[4]), int(p[5])))
+            elif p[0] == "L":
+                v = np.array([float(x) for x in p[4:]])
+                links.setdefault(int(p[1]), []).append((int(p[2]), int(p[3]), (v[0::2] + 1j * v[1::2]).reshape(3, 3)))
+    return sweeps, links
+
+
+def _run_c2(precision, link_sweeps, samples):
+    """The first len(fixture) sweeps of the 32^3 x 64 workload on the GPU, with
+    the sampled links read back after the sweeps in link_sweeps."""
+    c = fieldgen.CONFIGS["c2"]
+    dims = c["dims"]
+    n = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
+    pairs = fieldgen.centrifuge_pairs(dims, c["pair_seed"])
+    f = api.Field(dims, precision, device=torch.device("cuda:0"), jacobi_workspace=False)
+    f.set_charges(n)
+    api.precondition(f, pairs, c["omega"])
+    recs, got, done = [], {}, 0
+    for k in sorted(link_sweeps) + [100]:
+        if k > done:
+            st = api.smooth(f, k - done, c["rho"], c["eps"], order="annealed", vp=True, measure_every=1)
+            recs.append(api.stats_to_numpy(st, k - done))
+            done = k
+        if k in link_sweeps:
+            G = api.get_links(f)
+            mus = torch.as_tensor([mu for mu, s, u in samples[k]], device=G.device)
+            sites = torch.as_tensor([s for mu, s, u in samples[k]], device=G.device)
+            got[k] = G[mus, sites].cpu().numpy()
+            del G
+    torch.cuda.synchronize()
+    return np.concatenate(recs).view(np.recarray), got
+
+
+def test_c2_fixture_is_complete():
+    sweeps, links = _load_c2()
+    assert [s[0] for s in sweeps] == list(range(1, 101))
+    assert sorted(links) == [1, 2] and all(len(v) == 64 for v in links.values())
+    assert all(s[4] == 0 for s in sweeps)
+
+
+def test_c2_fp64_first_100_sweeps_match_oracle():
+    """32^3 x 64, FP64: plaquette and action of each of the first 100 sweeps
+    within 1e-12 relative (action: or 1e-13 absolute), rejections exact, no
+    vortex lost, sampled links after sweeps 1 and 2 within 1e-12."""
+    sweeps, links = _load_c2()
+    rec, got = _run_c2("fp64", (1, 2), links)
+    np.testing.assert_allclose(rec.plaq, [s[1] for s in sweeps], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(rec.action, [s[2] for s in sweeps], rtol=1e-12, atol=1e-13)
+    np.testing.assert_array_equal(rec.rejected, [s[3] for s in sweeps])
+    assert np.all(rec.flux_mismatch == 0) and np.all(rec.nonfinite == 0)
+    for k in (1, 2):
+        err = np.abs(got[k] - np.array([u for mu, s, u in links[k]])).max()
+        print(f"c2 fp64 sweep {k}: sampled link error {err:.2e}")
+        assert err < 1e-12
+
+
+def test_c2_fp32_bulk_first_100_sweeps_error_bound():
+    """32^3 x 64, FP32-bulk against the FP64 oracle, stated per result: the
+    lattice-averaged action of every sweep within 1e-3 relative, sampled links
+    after sweeps 1 and 2 within 2e-6, no vortex lost, no non-finite link."""
+    sweeps, links = _load_c2()
+    rec, got = _run_c2("fp32_bulk", (1, 2), links)
+    want = np.array([s[2] for s in sweeps])
+    rel = np.abs(rec.action - want) / want
+    errs = {k: np.abs(got[k] - np.array([u for mu, s, u in links[k]])).max() for k in (1, 2)}
+    print(f"c2 fp32_bulk action: max rel error {rel.max():.3e} (sweep {int(rel.argmax()) + 1}), "
+          f"final {rel[-1]:.3e}; sampled link errors {errs}; rejections {int(rec.rejected.sum())} vs "
+          f"oracle {sum(s[3] for s in sweeps)}")
+    assert np.all(rec.flux_mismatch == 0) and np.all(rec.nonfinite == 0)
+    assert rel.max() < 1e-3
+    assert all(e < 2e-6 for e in errs.values())
