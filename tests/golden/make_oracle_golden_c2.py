@@ -2,12 +2,12 @@
 
 Runs only oracle/ (and the seeded input generator): centrifuge preconditioning
 (omega = 0.02) of the Z(3) vortex field (p = 0.1, seeds 1002/2002), then the
-first 100 of the workload's annealed over-improved stout sweeps (rho = 0.06,
-eps = -0.25, u0 = 1) with vortex preservation.  Records plaquette, action and
-rejections after every sweep, and 64 sampled links after sweeps 1 and 2 (before
-the smoothing map has amplified rounding differences; the 16^3 x 32 fixture
-measures that amplification).
-Usage: python tests/golden/make_oracle_golden_c2.py   (about 40 minutes on 8 threads)
+workload's 500 annealed over-improved stout sweeps (rho = 0.06, eps = -0.25,
+u0 = 1) with vortex preservation (or the first N with an argument N).  Records
+plaquette, action and rejections after every sweep, and 64 sampled links after
+sweeps 1 and 2 (before the smoothing map has amplified rounding differences;
+the 16^3 x 32 fixture measures that amplification).
+Usage: python tests/golden/make_oracle_golden_c2.py [N]   (about 16 s a sweep on 8 threads)
 """
 import os
 import sys
@@ -21,8 +21,8 @@ sys.path.insert(0, ROOT)
 import fieldgen  # noqa: E402
 import oracle  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle_first100.txt")
-N_SWEEPS = 100
+N_SWEEPS = int(sys.argv[1]) if len(sys.argv) > 1 else 500
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_oracle_trajectory.txt")
 LINK_SWEEPS = (1, 2)
 N_SAMPLES = 64
 
@@ -49,7 +49,7 @@ def main():
     dt = time.time() - t
     with open(OUT, "w") as f:
         f.write("# FP64 oracle, 32^3x64 workload: Z(3) vortex field p=0.1 (seeds 1002/2002),\n")
-        f.write("# centrifuge omega=0.02, the first 100 annealed over-improved stout sweeps\n")
+        f.write("# centrifuge omega=0.02, the first %d annealed over-improved stout sweeps\n" % N_SWEEPS)
         f.write("# rho=0.06 eps=-0.25 u0=1 with vortex preservation (Sec. IV-VI).\n")
         f.write("# Written by tests/golden/make_oracle_golden_c2.py (oracle only); %.0f s on %d threads.\n"
                 % (dt, oracle.set_threads(0)))

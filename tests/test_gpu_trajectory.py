@@ -18,10 +18,10 @@ many sweeps two correct FP64 implementations differ by that much).  The
 FP32-bulk form is held to stated bounds on the action and link errors, with no
 vortex lost.
 
-The first 100 sweeps of the 32^3 x 64 workload (seeds 1002/2002, same recipe)
-are held to the same FP64 bars against tests/golden/c2_oracle_first100.txt
-(written by tests/golden/make_oracle_golden_c2.py), and the FP32-bulk form's
-per-sweep action error against the FP64 oracle is stated and bounded.
+The 500 sweeps of the 32^3 x 64 workload (seeds 1002/2002, same recipe) are
+held to the FP64 bars against tests/golden/c2_oracle_trajectory.txt (written
+by tests/golden/make_oracle_golden_c2.py), and the FP32-bulk form's per-sweep
+action error against the FP64 oracle is stated and bounded.
 """
 import os
 
@@ -130,7 +130,7 @@ def test_fp32_bulk_trajectory_error_bound():
 
 # ---------------------------------------------------------------- 32^3 x 64
 
-C2_FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle_first100.txt")
+C2_FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_oracle_trajectory.txt")
 
 
 def _load_c2():
@@ -148,9 +148,9 @@ def _load_c2():
     return sweeps, links
 
 
-def _run_c2(precision, link_sweeps, samples):
-    """The first len(fixture) sweeps of the 32^3 x 64 workload on the GPU, with
-    the sampled links read back after the sweeps in link_sweeps."""
+def _run_c2(precision, link_sweeps, samples, n_sweeps=500):
+    """The 500 sweeps of the 32^3 x 64 workload on the GPU, with the sampled
+    links read back after the sweeps in link_sweeps."""
     c = fieldgen.CONFIGS["c2"]
     dims = c["dims"]
     n = fieldgen.z3_vortex_charges(dims, c["p"], c["field_seed"])
@@ -159,7 +159,7 @@ def _run_c2(precision, link_sweeps, samples):
     f.set_charges(n)
     api.precondition(f, pairs, c["omega"])
     recs, got, done = [], {}, 0
-    for k in sorted(link_sweeps) + [100]:
+    for k in sorted(link_sweeps) + [n_sweeps]:
         if k > done:
             st = api.smooth(f, k - done, c["rho"], c["eps"], order="annealed", vp=True, measure_every=1)
             recs.append(api.stats_to_numpy(st, k - done))
@@ -176,15 +176,15 @@ def _run_c2(precision, link_sweeps, samples):
 
 def test_c2_fixture_is_complete():
     sweeps, links = _load_c2()
-    assert [s[0] for s in sweeps] == list(range(1, 101))
+    assert [s[0] for s in sweeps] == list(range(1, 501))
     assert sorted(links) == [1, 2] and all(len(v) == 64 for v in links.values())
     assert all(s[4] == 0 for s in sweeps)
 
 
-def test_c2_fp64_first_100_sweeps_match_oracle():
-    """32^3 x 64, FP64: plaquette and action of each of the first 100 sweeps
-    within 1e-12 relative (action: or 1e-13 absolute), rejections exact, no
-    vortex lost, sampled links after sweeps 1 and 2 within 1e-12."""
+def test_c2_fp64_trajectory_matches_oracle():
+    """32^3 x 64, FP64: plaquette and action of each of the 500 sweeps within
+    1e-12 relative (action: or 1e-13 absolute), rejections exact, no vortex
+    lost, sampled links after sweeps 1 and 2 within 1e-12."""
     sweeps, links = _load_c2()
     rec, got = _run_c2("fp64", (1, 2), links)
     np.testing.assert_allclose(rec.plaq, [s[1] for s in sweeps], rtol=1e-12, atol=0)
@@ -197,7 +197,7 @@ def test_c2_fp64_first_100_sweeps_match_oracle():
         assert err < 1e-12
 
 
-def test_c2_fp32_bulk_first_100_sweeps_error_bound():
+def test_c2_fp32_bulk_trajectory_error_bound():
     """32^3 x 64, FP32-bulk against the FP64 oracle, stated per result: the
     lattice-averaged action of every sweep within 1e-3 relative, sampled links
     after sweeps 1 and 2 within 2e-6, no vortex lost, no non-finite link."""
