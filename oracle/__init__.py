@@ -34,9 +34,13 @@ STATS_DTYPE = np.dtype([
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so with gcc (FP64, IEEE, OpenMP)."""
     if force or not os.path.exists(LIB_PATH):
+        # written beside the library and renamed over it, so that a process that
+        # has the old one loaded keeps a valid mapping
+        tmp = LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11", "-Wall",
-               SRC_PATH, "-o", LIB_PATH, "-lm"]
+               SRC_PATH, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
 
@@ -74,7 +78,7 @@ def lib():
                                         i32, P]),
             "ora_smooth": (ctypes.c_int, [P, P, P, P, i32, i32, i32, i32, f64, f64, f64, f64,
                                           i32, i32, P]),
-            "ora_measure": (ctypes.c_int, [P, P, P, P, P]),
+            "ora_measure": (ctypes.c_int, [P, P, P, P, P, P]),
             "ora_sectors": (ctypes.c_int, [P, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -246,12 +250,15 @@ def smooth(dims, links, n0, n_sweeps, *, order="annealed", update="stout", vp=Fa
     return stats[:nrec].view(np.recarray)
 
 
-def measure(dims, links, n0, with_flux=False):
+def measure(dims, links, n0, with_flux=False, gauge=None):
+    """One stats record; with a gauge G (complex128 [V,3,3]) the centre sectors
+    of the links are those of G^dag(x) U G(x+mu)."""
     links = np.ascontiguousarray(links, dtype=np.complex128)
     n0 = np.ascontiguousarray(n0, dtype=np.int8)
+    gauge = None if gauge is None else np.ascontiguousarray(gauge, dtype=np.complex128)
     st = np.zeros(1, dtype=STATS_DTYPE)
     flux = np.empty((6, _vol(dims)), dtype=np.int8) if with_flux else None
-    _check(lib().ora_measure(_p(_dims(dims)), _p(links), _p(n0), _p(st), _p(flux)), "measure")
+    _check(lib().ora_measure(_p(_dims(dims)), _p(links), _p(n0), _p(gauge), _p(st), _p(flux)), "measure")
     rec = st.view(np.recarray)[0]
     return (rec, flux) if with_flux else rec
 

@@ -702,8 +702,8 @@ int ora_pass(const int32_t dims[4], double *links, const int8_t *n0, const doubl
   return ORA_OK;
 }
 
-static int measure(const lattice *g, const double *links, const int8_t *n0, ora_stats *out,
-                   int8_t *flux);
+static int measure(const lattice *g, const double *links, const int8_t *n0, const double *gauge,
+                   ora_stats *out, int8_t *flux);
 
 /* n_sweeps sweeps.  JACOBI (smearing, Sec. III.A): every link is updated from
  * the field of the previous sweep.  ANNEALED: for mu = 0..3, subsets 0, 2, 1, 3
@@ -756,7 +756,7 @@ int ora_smooth(const int32_t dims[4], double *links, const int8_t *n0, const dou
           rej_since += anneal_subset(&g, links, n0, gauge, &pr, mu, colours[c]);
     }
     if (measure_every > 0 && (sw + 1) % measure_every == 0) {
-      measure(&g, links, n0, &stats[rec], NULL);
+      measure(&g, links, n0, gauge, &stats[rec], NULL);
       stats[rec].rejected = rej_since;
       rej_since = 0;
       ++rec;
@@ -874,9 +874,13 @@ static void ks_add(ksum *k, long double v) {
  * Re Tr[1 - P_{mu nu}(x)] (Sec. V), reported as <S>/beta with n_c = 3, n_d = 4
  * and the ordered sum written as twice the sum over mu < nu; the vortex flux
  * p_{mu nu}(x) of the projected plaquette (Sec. I) from the centre projections
- * of the current links, compared with the flux of the original charges n0. */
-static int measure(const lattice *g, const double *links, const int8_t *n0, ora_stats *out,
-                   int8_t *flux) {
+ * of the current links, compared with the flux of the original charges n0.
+ * The charges n0 belong to the field in maximal centre gauge; when the field
+ * lives in a random gauge G (Sec. V.C), a link's centre projection is taken
+ * after undoing it, from G^dagger(x) U G(x + mu), as the vortex-preserving test
+ * of Sec. VI does. */
+static int measure(const lattice *g, const double *links, const int8_t *n0, const double *gauge,
+                   ora_stats *out, int8_t *flux) {
   const int64_t V = g->V;
   long double *site_p = (long double *)malloc(sizeof(long double) * (size_t)V);
   long double *site_s = (long double *)malloc(sizeof(long double) * (size_t)V);
@@ -905,7 +909,15 @@ static int measure(const lattice *g, const double *links, const int8_t *n0, ora_
           double dv = cabs(uu.a[i][j] - (i == j ? 1.0 : 0.0));
           if (dv > maxu) maxu = dv;
         }
-      int sc = sector_of(&u);
+      mat3 mcg = u;
+      if (gauge) {
+        mat3 G = m_load(gauge + 18 * (size_t)s);
+        mat3 Gp = m_load(gauge + 18 * (size_t)fwd(g, s, mu));
+        mat3 Gd = m_dag(&G);
+        mat3 t = m_mul(&Gd, &u);
+        mcg = m_mul(&t, &Gp);
+      }
+      int sc = sector_of(&mcg);
       if (sc == ORA_UNDEF) ++undef;
       sec[(size_t)mu * V + s] = (int8_t)sc;
     }
@@ -1102,13 +1114,13 @@ double ora_correlation(int64_t n, const double *a, const double *b) {
   return (double)(sab / sqrtl(saa * sbb));
 }
 
-int ora_measure(const int32_t dims[4], const double *links, const int8_t *n0, ora_stats *out,
-                int8_t *flux) {
+int ora_measure(const int32_t dims[4], const double *links, const int8_t *n0, const double *gauge,
+                ora_stats *out, int8_t *flux) {
   if (!links || !n0 || !out) return ORA_E_NULL;
   lattice g;
   int rc = lat_init(&g, dims);
   if (rc) return rc;
-  rc = measure(&g, links, n0, out, flux);
+  rc = measure(&g, links, n0, gauge, out, flux);
   lat_free(&g);
   return rc;
 }

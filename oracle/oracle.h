@@ -84,8 +84,8 @@ int ora_smooth(const int32_t dims[4], double *links, const int8_t *n0, const dou
                int32_t n_sweeps, int32_t order, int32_t update, int32_t vp, double rho,
                double eps, double u0, double alpha, int32_t su2_loops, int32_t measure_every,
                ora_stats *stats);
-int ora_measure(const int32_t dims[4], const double *links, const int8_t *n0, ora_stats *out,
-                int8_t *flux);
+int ora_measure(const int32_t dims[4], const double *links, const int8_t *n0, const double *gauge,
+                ora_stats *out, int8_t *flux);
 int ora_sectors(const int32_t dims[4], const double *links, int8_t *out);
 
 /* n_steps Wilson-flow steps of size eps on every link at once; integrator 0 =

@@ -20,7 +20,7 @@ vortex lost.
 
 The 500 sweeps of the 32^3 x 64 workload (seeds 1002/2002, same recipe) are
 held to the FP64 bars against tests/golden/c2_oracle_trajectory.txt (written
-by tests/golden/make_oracle_golden_c2.py), and the FP32-bulk form's per-sweep
+by tests/golden/make_oracle_trajectory.py c2), and the FP32-bulk form's per-sweep
 action error against the FP64 oracle is stated and bounded.
 """
 import os

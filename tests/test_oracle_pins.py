@@ -453,6 +453,55 @@ def test_plain_staples_even_subsets_commute(ora):
             np.testing.assert_array_equal(a[1, s], want)
 
 
+def _np_plain_stout(dims, U, mu, sites, rho):
+    """Plain-staple stout updates (Eq. plaq_staples, Eq. generator, Eq. stout) of
+    the links (mu, s) for s in sites, all from the field U, in numpy with
+    scipy's matrix exponential (no oracle code)."""
+    V = fieldgen.volume(dims)
+    S = np.zeros((V, 3, 3), dtype=complex)
+    up = fieldgen.neighbour(dims, mu, 1)
+    for nu in range(4):
+        if nu == mu:
+            continue
+        vp, vm = fieldgen.neighbour(dims, nu, 1), fieldgen.neighbour(dims, nu, -1)
+        S += U[nu] @ U[mu][vp] @ _loops.dag(U[nu][up])
+        S += _loops.dag(U[nu][vm]) @ U[mu][vm] @ U[nu][vm][up]
+    om = S[sites] @ _loops.dag(U[mu][sites])
+    A = 0.5 * (om - _loops.dag(om))
+    Q = A - np.trace(A, axis1=1, axis2=2)[:, None, None] / 3 * np.eye(3)
+    return scipy.linalg.expm(rho * Q) @ U[mu][sites]
+
+
+def test_annealed_sweep_is_direction_then_parity(ora):
+    """Sec. III.A and the direction/parity subset order: with plain staples an
+    annealed sweep takes, for mu = 0..3, first every link whose coordinates
+    off the mu axis sum to an even number, all from the current field, then the
+    odd ones from the field that includes the even updates.  Built in numpy from
+    the definitions; a different subset or direction order fails."""
+    dims = SMALL
+    U = _haar_field(dims, 141)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 142)
+    V = fieldgen.volume(dims)
+    coords = np.stack([np.arange(V) // int(np.prod(dims[:d])) % dims[d] for d in range(4)])
+    want = U.copy()
+    for mu in range(4):
+        par = (coords.sum(axis=0) - coords[mu]) % 2
+        for p in (0, 1):
+            sites = np.nonzero(par == p)[0]
+            want[mu][sites] = _np_plain_stout(dims, want, mu, sites, 0.2)
+    got = U.copy()
+    ora.smooth(dims, got, n, 1, order="annealed", rho=0.2, eps=1.0, measure_every=0)
+    np.testing.assert_allclose(got, want, atol=1e-13)
+    # the same sweep with the parities the other way round is a different map
+    other = U.copy()
+    for mu in range(4):
+        par = (coords.sum(axis=0) - coords[mu]) % 2
+        for p in (1, 0):
+            sites = np.nonzero(par == p)[0]
+            other[mu][sites] = _np_plain_stout(dims, other, mu, sites, 0.2)
+    assert np.abs(other - want).max() > 1e-3
+
+
 def test_annealed_flow_decreases_wilson_action(ora):
     """Sec. II.B / V.B: annealed stout with plain staples and a small step is an
     Euler step of the Wilson flow, which lowers the Wilson action monotonically."""
@@ -526,6 +575,33 @@ def test_vp_in_random_gauge(ora):
                     measure_every=0)
     assert sa["rejected"].sum() > 0
     np.testing.assert_allclose(B, ora.gauge_transform(dims, A, G), atol=1e-12)
+    # the vortex content measured in the random gauge (centre projections of
+    # G^dag(x) U G(x+mu)) is the MCG field's: no plaquette changed its flux
+    ma, fa = ora.measure(dims, A, n, with_flux=True)
+    mb, fb = ora.measure(dims, B, n, with_flux=True, gauge=G)
+    np.testing.assert_array_equal(fa, fb)
+    assert ma.flux_mismatch == 0 and mb.flux_mismatch == 0
+    assert abs(ma.plaq - mb.plaq) < 1e-13
+    sc = ora.smooth(dims, B.copy(), n, 2, order="annealed", rho=0.4, eps=-0.25, vp=True, gauge=G)
+    assert np.all(sc["flux_mismatch"] == 0) and np.all(sc["undefined_sector"] == 0)
+
+
+def test_measure_undoes_a_random_gauge(ora):
+    """Sec. I, V.C: the vortex flux of a Z(3) field is the lattice curl of its
+    seed s; after a random gauge transform the links are no longer centre
+    elements, and the flux is recovered only by projecting G^dag(x) U G(x+mu)."""
+    dims = SMALL
+    n, g, sd = fieldgen.z3_vortex_charges(dims, 0.2, 165, return_parts=True)
+    U = ora.z3_field(dims, n)
+    G = fieldgen.haar_su3(fieldgen.volume(dims), 166)
+    W = ora.gauge_transform(dims, U, G)
+    st0, f0 = ora.measure(dims, U, n, with_flux=True)
+    st1, f1 = ora.measure(dims, W, n, with_flux=True, gauge=G)
+    np.testing.assert_array_equal(f0, f1)
+    assert st1.flux_mismatch == 0 and st1.undefined_sector == 0
+    assert abs(st1.plaq - st0.plaq) < 1e-14
+    st2 = ora.measure(dims, W, n)  # sectors of the transformed links themselves
+    assert st2.flux_mismatch > 0
 
 
 # ------------------------------------------------------------- MaxReTr
@@ -563,6 +639,41 @@ def test_maxretr_centre_closed_form(ora):
                 assert np.abs(out - Z).max() > 0.1
                 assert np.trace(out @ V.conj().T).real > np.trace(Z @ V.conj().T).real
                 np.testing.assert_allclose(out @ out.conj().T, np.eye(3), atol=1e-14)
+
+
+def test_maxretr_centre_one_loop_fixture(ora):
+    """Sec. III, Eqs. (def_L1), (def_T1) and the T_2, T_3 matrices: one loop over
+    the subgroups (1,2), (2,3), (1,3) on a centre link with r cos(phi) < 0 and
+    sin(phi) != 0, against the hand derivation in maxretr_centre_one_loop.txt
+    (the subgroup order decides the result)."""
+    rows = _rows("maxretr_centre_one_loop.txt")
+    assert len(rows) == 4
+    for n, r, th, p0, p1, p2 in rows:
+        n, r, th = int(n), float(r), float(th) * np.pi
+        U = np.exp(2j * np.pi * n / 3) * np.eye(3)
+        V = r * np.exp(1j * th) * np.eye(3)
+        want = np.diag(np.exp(1j * np.pi * np.array([float(p0), float(p1), float(p2)])))
+        np.testing.assert_allclose(ora.maxretr(U, V, loops=1), want, atol=1e-14)
+
+
+@pytest.mark.parametrize("block", [(0, 1), (1, 2), (0, 2)])
+def test_maxretr_single_subgroup_hit(ora, block):
+    """Sec. III: if L^1 = U V^dagger is r times an SU(2) matrix W embedded in the
+    rows/columns of one subgroup (W's diagonal real, 1 on the remaining
+    diagonal entry), every other hit sees an identity-proportional block and
+    leaves U alone, while that subgroup's hit gives T = r W, k = r and
+    U <- W^dagger U, after which L = r 1.  So one loop, and three, return
+    W^dagger U exactly; an index or conjugation slip in any subgroup's T fails."""
+    p, q = block
+    U = fieldgen.haar_su3(1, 231 + p + 3 * q)[0]
+    a, b = 0.6, 0.48 + 0.64j  # a^2 + |b|^2 = 1
+    E = np.eye(3, dtype=complex)
+    E[p, p], E[p, q], E[q, p], E[q, q] = a, b, -np.conj(b), a
+    r = 1.7
+    V = (r * E).conj().T @ U  # L = U V^dagger = r E
+    want = E.conj().T @ U
+    for loops in (1, 3):
+        np.testing.assert_allclose(ora.maxretr(U, V, loops=loops), want, atol=1e-14)
 
 
 def test_alpha_min_threshold(ora):
