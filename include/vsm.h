@@ -168,10 +168,13 @@ int vsm_pass(const int32_t dims[4], int32_t precision, void *links_dev, const in
 /* Sec. I, V.A: one vsm_stats record of links_dev into stats_dev (device); the
  * vortex flux p_{mu nu}(x) in {-1, 0, 1} of the current links' centre projections
  * into flux_dev (device int8 [6][V], planes 01, 02, 03, 12, 13, 23; -128 where a
- * sector is undefined) when not NULL.  The rejected field reports the count
- * accumulated in the workspace since the last record and clears it. */
+ * sector is undefined) when not NULL.  gauge_dev (nullable, as for vsm_smooth):
+ * the field lives in that random gauge (Sec. V.C), and a link's centre
+ * projection is taken from G^dagger(x) U G(x + mu), where the original charges
+ * z3_dev live.  The rejected field reports the count accumulated in the
+ * workspace since the last record and clears it. */
 int vsm_measure(const int32_t dims[4], int32_t precision, const void *links_dev, const int8_t *z3_dev,
-                void *workspace_dev, size_t workspace_bytes, vsm_stats *stats_dev,
+                const double *gauge_dev, void *workspace_dev, size_t workspace_bytes, vsm_stats *stats_dev,
                 int8_t *flux_dev, void *stream);
 
 /* Sec. II.B, V.B: n_steps steps of size eps of the Wilson flow

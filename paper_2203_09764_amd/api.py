@@ -124,6 +124,15 @@ def stats_to_numpy(t: torch.Tensor, n: int | None = None) -> np.recarray:
     return a.view(np.recarray)
 
 
+def _check_stats(stats, nrec, device):
+    """The library writes nrec records of STATS_BYTES into stats without a bound:
+    refuse a tensor that cannot hold them."""
+    if (not isinstance(stats, torch.Tensor) or stats.dtype != torch.uint8 or stats.device != torch.device(device)
+            or not stats.is_contiguous() or stats.numel() < nrec * STATS_BYTES):
+        raise ValueError(f"stats must be a contiguous uint8 tensor on {device} with at least "
+                         f"{nrec * STATS_BYTES} bytes ({nrec} records)")
+
+
 def smooth(field: Field, n_sweeps, rho, eps, *, order="annealed", update="stout", vp=False,
            u0=1.0, alpha=1.0, su2_loops=3, gauge=None, measure_every=0, stats=None, stream=None):
     """n_sweeps sweeps (include/vsm.h, vsm_smooth).  Returns the device stats
@@ -132,6 +141,8 @@ def smooth(field: Field, n_sweeps, rho, eps, *, order="annealed", update="stout"
     nrec = n_sweeps // measure_every if measure_every > 0 else 0
     if measure_every > 0 and stats is None:
         stats = new_stats(nrec, field.device)
+    if measure_every > 0:
+        _check_stats(stats, nrec, field.device)
     G = None
     if gauge is not None:
         G = torch.as_tensor(gauge).to(device=field.device, dtype=torch.complex128).contiguous()
@@ -156,11 +167,15 @@ def anneal_pass(field: Field, mu, colour, rho, eps, *, update="stout", vp=False,
           "vsm_pass")
 
 
-def measure(field: Field, with_flux=False, stream=None):
-    """Sec. I, V.A: one stats record (device tensor) and optionally the flux int8 [6][V]."""
+def measure(field: Field, with_flux=False, gauge=None, stream=None):
+    """Sec. I, V.A: one stats record (device tensor) and optionally the flux int8 [6][V];
+    with a gauge (complex128 [V,3,3]) the link sectors are taken after undoing it."""
     st = new_stats(1, field.device)
     flux = torch.empty((6, field.V), dtype=torch.int8, device=field.device) if with_flux else None
-    check(lib().vsm_measure(dims_arg(field.dims), field.precision, _ptr(field.links), _ptr(field.z3),
+    G = None
+    if gauge is not None:
+        G = torch.as_tensor(gauge).to(device=field.device, dtype=torch.complex128).contiguous()
+    check(lib().vsm_measure(dims_arg(field.dims), field.precision, _ptr(field.links), _ptr(field.z3), _ptr(G),
                             _ptr(field.workspace), field.workspace.numel(), _ptr(st), _ptr(flux),
                             _stream(stream)), "vsm_measure")
     return (st, flux) if with_flux else st

@@ -109,24 +109,25 @@ int vsm_gauge_transform(const int32_t dims[4], int32_t precision, void* links_de
   return hip_status();
 }
 
-int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const int8_t* z3_dev,
-               const double* gauge_dev, void* workspace_dev, size_t workspace_bytes,
-               int32_t n_sweeps, double rho, double eps, const vsm_schedule* sched,
-               int32_t measure_every, vsm_stats* stats_dev, void* stream) {
+}  // extern "C"
+
+namespace vsm {
+
+int smooth_impl(const int32_t dims[4], int32_t precision, void* links_dev, const int8_t* z3_dev,
+                const double* gauge_dev, char* ws, size_t ws_bytes, int32_t n_sweeps, double rho, double eps,
+                const vsm_schedule* sched, int32_t measure_every, vsm_stats* stats_dev, hipStream_t st) {
   int rc = check_sched(sched);
   if (rc) return rc;
   rc = check_dims_impl(dims, sched->order, precision);
   if (rc) return rc;
-  if (!links_dev || !workspace_dev) return VSM_E_NULL;
+  if (!links_dev || !ws) return VSM_E_NULL;
   if (n_sweeps < 0 || measure_every < 0 || !is_fin(rho) || !is_fin(eps)) return VSM_E_PARAM;
   if ((sched->vp || measure_every > 0) && !z3_dev) return VSM_E_NULL;
   if (measure_every > 0 && !stats_dev) return VSM_E_NULL;
   const WsLayout w = ws_layout(dims, precision, sched->order);
-  if (workspace_bytes < w.total) return VSM_E_WORKSPACE;
+  if (ws_bytes < w.total) return VSM_E_WORKSPACE;
   const Geo g = make_geo(dims);
   const UpdParams p = make_params(rho, eps, sched);
-  hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace_dev;
   unsigned long long* rej = (unsigned long long*)(ws + w.counters);
   VsmStatsDev* out = (VsmStatsDev*)stats_dev;
   // the measurement reads the charges in the internal layout
@@ -153,7 +154,7 @@ int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const 
                         rej, st);
     }
     if (measure_every > 0 && (sw + 1) % measure_every == 0) {
-      launch_measure(precision, g, cur, z3i, ws + w.partials, nullptr, rej, out + rec, sw + 1, st);
+      launch_measure(precision, g, cur, z3i, gauge_dev, ws + w.partials, nullptr, rej, out + rec, sw + 1, st);
       ++rec;
     }
   }
@@ -163,6 +164,18 @@ int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const 
     if (e != hipSuccess) return note_hip_error(e);
   }
   return hip_status();
+}
+
+}  // namespace vsm
+
+extern "C" {
+
+int vsm_smooth(const int32_t dims[4], int32_t precision, void* links_dev, const int8_t* z3_dev,
+               const double* gauge_dev, void* workspace_dev, size_t workspace_bytes,
+               int32_t n_sweeps, double rho, double eps, const vsm_schedule* sched,
+               int32_t measure_every, vsm_stats* stats_dev, void* stream) {
+  return smooth_impl(dims, precision, links_dev, z3_dev, gauge_dev, (char*)workspace_dev, workspace_bytes, n_sweeps,
+                     rho, eps, sched, measure_every, stats_dev, (hipStream_t)stream);
 }
 
 int vsm_pass(const int32_t dims[4], int32_t precision, void* links_dev, const int8_t* z3_dev,
@@ -186,8 +199,8 @@ int vsm_pass(const int32_t dims[4], int32_t precision, void* links_dev, const in
 }
 
 int vsm_measure(const int32_t dims[4], int32_t precision, const void* links_dev, const int8_t* z3_dev,
-                void* workspace_dev, size_t workspace_bytes, vsm_stats* stats_dev, int8_t* flux_dev,
-                void* stream) {
+                const double* gauge_dev, void* workspace_dev, size_t workspace_bytes, vsm_stats* stats_dev,
+                int8_t* flux_dev, void* stream) {
   int rc = check_dims_impl(dims, VSM_JACOBI, precision);
   if (rc) return rc;
   if (!links_dev || !z3_dev || !workspace_dev || !stats_dev) return VSM_E_NULL;
@@ -197,7 +210,7 @@ int vsm_measure(const int32_t dims[4], int32_t precision, const void* links_dev,
   const Geo g = make_geo(dims);
   hipStream_t st = (hipStream_t)stream;
   launch_charges(g, z3_dev, (int8_t*)(ws + w.charges), 0, 4, st);
-  launch_measure(precision, g, links_dev, (const int8_t*)(ws + w.charges), ws + w.partials, flux_dev,
+  launch_measure(precision, g, links_dev, (const int8_t*)(ws + w.charges), gauge_dev, ws + w.partials, flux_dev,
                  (unsigned long long*)(ws + w.counters), (VsmStatsDev*)stats_dev, -1, st);
   return hip_status();
 }

@@ -134,6 +134,12 @@ inline UpdParams make_params(double rho, double eps, const vsm_schedule* s) {
   p.cr = (eps - 1.0) / (12.0 * s->u0 * s->u0);
   p.rho = rho;
   p.alpha = s->alpha;
+  // rounding level of Q: the staple sum adds 6 plaquette and 18 rectangle
+  // paths of SU(3) matrices (entries at most 1) with weights c_p and c_r, each
+  // carrying a few roundings; 2^-48 (32 units of FP64 rounding) times the sum of
+  // the weights.  A centre field's Q stays below it; a generator that small
+  // moves a link by less than 1e-13.
+  p.qfloor = 3.552713678800501e-15 * (6.0 * fabs(p.cp) + 18.0 * fabs(p.cr));
   p.update = s->update == VSM_MAXRETR ? 1 : (s->update == VSM_APE ? 2 : 0);
   p.oi = p.cr != 0.0 ? 1 : 0;
   p.vp = s->vp ? 1 : 0;
@@ -143,5 +149,11 @@ inline UpdParams make_params(double rho, double eps, const vsm_schedule* s) {
 
 // Subset order of one direction in an annealed sweep.
 constexpr int kColours[4] = {0, 2, 1, 3};
+
+// The sweeps of vsm_smooth (validation included) on a device workspace of
+// ws_bytes bytes at ws.
+int smooth_impl(const int32_t dims[4], int32_t precision, void* links_dev, const int8_t* z3_dev,
+                const double* gauge_dev, char* ws, size_t ws_bytes, int32_t n_sweeps, double rho, double eps,
+                const vsm_schedule* sched, int32_t measure_every, vsm_stats* stats_dev, hipStream_t st);
 
 }  // namespace vsm

@@ -10,7 +10,7 @@ template void launch_centrifuge_t<float>(const Geo&, const int8_t*, const int8_t
 template void launch_gauge_t<float>(const Geo&, void*, const void*, hipStream_t);
 template void launch_update_t<float>(const Geo&, const void*, void*, const int8_t*, const void*,
                                  const UpdParams&, int, int, int, unsigned long long*, hipStream_t);
-template void launch_measure_t<float>(const Geo&, const void*, const int8_t*, void*, int8_t*,
+template void launch_measure_t<float>(const Geo&, const void*, const int8_t*, const void*, void*, int8_t*,
                                   unsigned long long*, VsmStatsDev*, long long, hipStream_t);
 template void launch_update_batch_t<float>(const ServeJob*, const BatchStep&, uint32_t, hipStream_t);
 template void launch_clover_t<float>(const Geo&, const void*, void*, double*, double*, double*, hipStream_t);

@@ -24,7 +24,7 @@ void launch_clover_t(const Geo&, const void*, void*, double*, double*, double*, 
 template <typename R>
 void launch_flow_t(const Geo&, const void*, void*, double*, int, double, double, double, hipStream_t);
 template <typename R>
-void launch_measure_t(const Geo&, const void*, const int8_t*, void*, int8_t*, unsigned long long*,
+void launch_measure_t(const Geo&, const void*, const int8_t*, const void*, void*, int8_t*, unsigned long long*,
                       VsmStatsDev*, long long, hipStream_t);
 
 // Clears n 64-bit counters (a kernel rather than a memset, so that the call can
@@ -163,11 +163,11 @@ void launch_correlate(long long n, const double* a, const double* b, double* out
 uint32_t measure_blocks(const Geo& g) { return (g.V + 255u) / 256u; }
 size_t partial_bytes() { return 80; }
 
-void launch_measure(int prec, const Geo& g, const void* links, const int8_t* z3, void* partials,
-                    int8_t* flux, unsigned long long* rej, VsmStatsDev* out, long long sweep,
+void launch_measure(int prec, const Geo& g, const void* links, const int8_t* z3, const void* gauge,
+                    void* partials, int8_t* flux, unsigned long long* rej, VsmStatsDev* out, long long sweep,
                     hipStream_t st) {
-  if (prec == 0) launch_measure_t<double>(g, links, z3, partials, flux, rej, out, sweep, st);
-  else launch_measure_t<float>(g, links, z3, partials, flux, rej, out, sweep, st);
+  if (prec == 0) launch_measure_t<double>(g, links, z3, gauge, partials, flux, rej, out, sweep, st);
+  else launch_measure_t<float>(g, links, z3, gauge, partials, flux, rej, out, sweep, st);
 }
 
 }  // namespace vsm

@@ -275,12 +275,14 @@ __device__ __forceinline__ M3<R> stout_h(const M3<R>& S, const M3<R>& U, double 
 }
 
 // out = exp(i H) U for Hermitian traceless H, by Cayley-Hamilton with FP64
-// coefficients, then FP64 reunitarisation.  H = 0 returns false (U unchanged).
+// coefficients, then FP64 reunitarisation.  Returns false (U unchanged) when
+// c1 = Tr H^2 / 2 does not exceed c1_floor: H = 0, or H below the rounding
+// level its caller states.
 template <typename R>
-__device__ __forceinline__ bool exp_apply(const M3<R>& H, const M3<R>& U, M3<double>& out) {
+__device__ __forceinline__ bool exp_apply(const M3<R>& H, const M3<R>& U, M3<double>& out, double c1_floor = 0.0) {
   double c0, c1;
   ch_invariants(H, c0, c1);
-  if (c1 == 0.0) return false;
+  if (c1 <= c1_floor) return false;  // a NaN carries on, so that it is counted
   const CHCoef f = ch_coefficients(c0, c1);
   // E = f0 + f1 H + f2 H^2 in the working precision
   const M3<R> H2 = mul_nn(H, H);
@@ -304,11 +306,19 @@ __device__ __forceinline__ bool exp_apply(const M3<R>& H, const M3<R>& U, M3<dou
 }
 
 // Stout (Eq. stout, Eq. generator): Omega = Sigma U^dag, Q its traceless
-// anti-Hermitian part, X = rho Q, U' = exp(X) U.  Q = 0 returns U unchanged.
+// anti-Hermitian part, X = rho Q, U' = exp(X) U.  Q = 0 returns U unchanged
+// (Sec. II.A: a centre field, whose staples are proportional to 1, does not
+// move).  Q counts as 0 when |Q|_F <= q_floor (UpdParams::qfloor, a few dozen
+// FP64 roundings of the staple sum's terms): a stored link's row 2 is rebuilt
+// from rows 0 and 1 with a rounding error, so for a centre field Omega is
+// proportional to 1 only up to the rounding of the paths summed into Sigma.
 template <typename R>
-__device__ __forceinline__ bool stout_candidate(const M3<R>& S, const M3<R>& U, double rho,
+__device__ __forceinline__ bool stout_candidate(const M3<R>& S, const M3<R>& U, double rho, double q_floor,
                                                 M3<double>& out) {
-  return exp_apply(stout_h(S, U, rho), U, out);
+  const M3<R> H = stout_h(S, U, rho);
+  // c1 = |H|_F^2 / 2 = rho^2 |Q|_F^2 / 2
+  const double rq = rho * q_floor;
+  return exp_apply(H, U, out, 0.5 * rq * rq);
 }
 
 // MaxReTr (Eq. maxReTr, def_L1, def_T1): V = (1 - alpha) U + (alpha/6) Sigma,
@@ -608,7 +618,7 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
     M3<double> cand;
     bool moved;
     if (UPD == 0)
-      moved = stout_candidate<R>(S, U, p.rho, cand);
+      moved = stout_candidate<R>(S, U, p.rho, p.qfloor, cand);
     else if (UPD == 1)
       moved = maxretr_candidate<R>(S, U, p.alpha, p.loops, cand);
     else
@@ -792,6 +802,20 @@ __device__ __forceinline__ int link_sector(const M3<double>& u) {
   return z3_sector(t.re, t.im);
 }
 
+// Centre sector of the link u = U_d(x) (internal direction d, site c) in
+// maximal centre gauge: with a gauge field G (the field lives in that random
+// gauge, Sec. V.C) the sector of G^dagger(x) u G(x + d), as the vortex-preserving
+// test of Sec. VI takes it; without one, the sector of u itself.
+template <bool GAUGE>
+__device__ __forceinline__ int mcg_sector(const Geo& g, const double2* __restrict__ gauge, const M3<double>& u,
+                                          const int c[4], int d) {
+  if (!GAUGE) return link_sector(u);
+  int cp[4] = {c[0], c[1], c[2], c[3]};
+  cp[d] = wrap_add(cp[d], 1, g.L[d]);
+  const Cx<double> t = gauge_undone_trace(gauge, canonical_index(g, c), canonical_index(g, cp), u);
+  return z3_sector(t.re, t.im);
+}
+
 // Per site: the six plaquettes P_{mu nu}(x), mu < nu (Sec. I), summed as
 // Re Tr P and Re Tr[1 - P] (Sec. V.A); the sectors of the four links at x;
 // the vortex flux of every plaquette from the link sectors compared with the
@@ -800,10 +824,12 @@ __device__ __forceinline__ int link_sector(const M3<double>& u) {
 // site are read by the same or a nearby block and come from cache.
 // Planes use user axes; the original charges z3 are in the internal layout
 // (k_charges).  Block partials go to fixed slots; k_finalize sums them in a
-// fixed order, so the result does not depend on the scheduling.
-template <typename R>
+// fixed order, so the result does not depend on the scheduling.  With GAUGE,
+// link sectors are taken after undoing the gauge field (mcg_sector).
+template <typename R, bool GAUGE>
 __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const int8_t* __restrict__ z3,
-                                                 Partial* __restrict__ part, int8_t* __restrict__ flux) {
+                                                 const double2* __restrict__ gauge, Partial* __restrict__ part,
+                                                 int8_t* __restrict__ flux) {
   const uint32_t blk = xcd_block();
   KSum kp = {0.0, 0.0}, ka = {0.0, 0.0};
   double maxu2 = 0.0;  // largest |(U^dag U - 1)_ij|^2; its root is taken once per thread
@@ -820,7 +846,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
     auto byte_at = [](uint32_t w, int i) { return (int)(int8_t)((w >> (8 * i)) & 0xffu); };
     // sector, finiteness and unitarity of an own link, once per link
     auto own_checks = [&](const M3<double>& U, int mu) {
-      const int sc = link_sector(U);
+      const int sc = mcg_sector<GAUGE>(g, gauge, U, c, g.perm[mu]);
       secb |= (uint32_t)(sc & 0xff) << (8 * mu);
       bool fin = true;
 #pragma unroll
@@ -856,10 +882,10 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
       const M3<double> A = mconvert<double>(full(Ar));
       if (p == 0) own_checks(A, 0);
       const M3<double> B = mconvert<double>(full(Br));
-      const int sb = link_sector(B);
+      const int sb = mcg_sector<GAUGE>(g, gauge, B, cm, dn);
       M3<double> P = mul_nn(A, B);
       const M3<double> Cm = mconvert<double>(full(Cr));
-      const int sc = link_sector(Cm);
+      const int sc = mcg_sector<GAUGE>(g, gauge, Cm, cn, dm);
       P = mul_nd(P, Cm);
       const M3<double> D = mconvert<double>(full(Dr));
       if (mu == 0) own_checks(D, nu);
@@ -1296,10 +1322,15 @@ void launch_clover_t(const Geo& g, const void* links, void* partials, double* ou
 }
 
 template <typename R>
-void launch_measure_t(const Geo& g, const void* links, const int8_t* z3, void* partials, int8_t* flux,
-                      unsigned long long* rej, VsmStatsDev* out, long long sweep, hipStream_t st) {
+void launch_measure_t(const Geo& g, const void* links, const int8_t* z3, const void* gauge, void* partials,
+                      int8_t* flux, unsigned long long* rej, VsmStatsDev* out, long long sweep, hipStream_t st) {
   const unsigned nb = blocks_for(g.V, 256);
-  hipLaunchKernelGGL(k_measure<R>, dim3(nb), dim3(256), 0, st, g, links, z3, (Partial*)partials, flux);
+  if (gauge)
+    hipLaunchKernelGGL((k_measure<R, true>), dim3(nb), dim3(256), 0, st, g, links, z3, (const double2*)gauge,
+                       (Partial*)partials, flux);
+  else
+    hipLaunchKernelGGL((k_measure<R, false>), dim3(nb), dim3(256), 0, st, g, links, z3, nullptr,
+                       (Partial*)partials, flux);
   hipLaunchKernelGGL(k_finalize<R>, dim3(1), dim3(256), 0, st, (const Partial*)partials, nb,
                      1.0 / (18.0 * (double)g.V), 1.0 / (36.0 * (double)g.V), rej, out, sweep);
 }

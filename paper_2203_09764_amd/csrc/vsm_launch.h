@@ -15,6 +15,7 @@ struct UpdParams {
   double cr;     // rectangle weight (eps - 1)/(12 u0^2)
   double rho;    // stout step
   double alpha;  // APE blocking fraction (MaxReTr)
+  double qfloor; // stout: |Q|_F at or below which Q counts as 0 (rounding level)
   int update;    // 0 stout, 1 MaxReTr, 2 APE with unit circle projection
   int oi;        // rectangles present (eps != 1)
   int vp;        // vortex-preserving accept/reject
@@ -61,8 +62,10 @@ void launch_update(int prec, const Geo& g, const void* src, void* dst, const int
                    unsigned long long* rej, hipStream_t st);
 uint32_t measure_blocks(const Geo& g);
 size_t partial_bytes();
-void launch_measure(int prec, const Geo& g, const void* links, const int8_t* z3, void* partials,
-                    int8_t* flux, unsigned long long* rej, VsmStatsDev* out, long long sweep,
+// gauge: the field's random gauge G (canonical complex128 [V][3][3]) or null;
+// with it the link sectors are those of G^dagger(x) U G(x + mu).
+void launch_measure(int prec, const Geo& g, const void* links, const int8_t* z3, const void* gauge,
+                    void* partials, int8_t* flux, unsigned long long* rej, VsmStatsDev* out, long long sweep,
                     hipStream_t st);
 // Blocks of 256 threads one annealing pass of g takes.
 inline uint32_t pass_blocks(const Geo& g) { return (g.V4 + 255u) / 256u; }

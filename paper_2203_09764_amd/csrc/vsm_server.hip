@@ -194,7 +194,7 @@ class Server {
     char* d = j->dbase;
     const WsLayout w = ws_layout(j->desc.dims, j->desc.precision, VSM_ANNEALED);
     launch_measure(j->desc.precision, j->g, d + j->lay.links, (const int8_t*)(d + j->lay.ws + w.charges),
-                   d + j->lay.ws + w.partials, nullptr, (unsigned long long*)(d + j->lay.ws),
+                   nullptr, d + j->lay.ws + w.partials, nullptr, (unsigned long long*)(d + j->lay.ws),
                    (VsmStatsDev*)(d + j->lay.records) + j->rec, sweep, stream);
     ++j->rec;
     ++ctr.launches;

@@ -112,20 +112,69 @@ def test_measure_matches_oracle(kind):
     assert s.nonfinite == 0 and s.max_unitarity < 1e-14
 
 
-@pytest.mark.parametrize("eps", [1.0, -0.25])
-@pytest.mark.parametrize("mu,colour", [(0, 0), (0, 3), (1, 2), (2, 1), (3, 0)])
-def test_single_pass_full_su3(eps, mu, colour):
-    """One annealing subset on a Haar-random field (every SU(3) entry non-zero)."""
-    dims = (8, 4, 8, 12)
-    U = _haar(dims, 100 + mu)
-    n = fieldgen.z3_vortex_charges(dims, 0.1, 11)
+def test_measure_in_a_random_gauge_matches_oracle():
+    """Sec. V.C, VI: a preconditioned vortex field in a Haar-random gauge, measured
+    with the gauge: centre sectors of G^dag(x) U G(x+mu), so the flux is the
+    MCG field's (bit-exact against the oracle, no mismatch); measured without
+    it, the sectors of the rotated links give mismatches, as in the oracle."""
+    dims = (8, 8, 4, 8)
+    n = fieldgen.z3_vortex_charges(dims, 0.15, 71)
+    G = fieldgen.haar_su3(fieldgen.volume(dims), 72)
+    U = ora.gauge_transform(dims, ora.centrifuge(dims, n, fieldgen.centrifuge_pairs(dims, 73), 0.02), G)
     f = _field(dims)
     f.set_charges(n)
     api.set_links(f, torch.from_numpy(U))
-    api.anneal_pass(f, mu, colour, 0.3, eps)
+    st, flux = api.measure(f, with_flux=True, gauge=torch.from_numpy(G))
+    s = _stats(st, 1)[0]
+    o, oflux = ora.measure(dims, U, n, with_flux=True, gauge=G)
+    np.testing.assert_array_equal(flux.cpu().numpy(), oflux)
+    assert s.flux_mismatch == o.flux_mismatch == 0
+    assert s.undefined_sector == o.undefined_sector == 0
+    assert abs(s.plaq - o.plaq) <= 1e-13 * abs(o.plaq)
+    s2 = _stats(api.measure(f), 1)[0]
+    o2 = ora.measure(dims, U, n)
+    assert s2.flux_mismatch == o2.flux_mismatch > 0
+
+
+def _ch_branches(dims, U, mu, colour, rho, eps):
+    """How many links of the subset take each branch of the GPU's Cayley-Hamilton
+    coefficients (c1 = Tr H^2 / 2 < 0.5: series; otherwise the closed form),
+    with H = rho Q from the oracle's staples and generator."""
+    small = large = 0
+    for s in range(fieldgen.volume(dims)):
+        if ora.colour(dims, mu, s) != colour:
+            continue
+        Q = ora.generator(ora.staple(dims, U, mu, s, eps=eps) @ U[mu, s].conj().T)
+        c1 = 0.5 * rho * rho * float(np.sum(np.abs(Q) ** 2))
+        if c1 < 0.5:
+            small += 1
+        else:
+            large += 1
+    return small, large
+
+
+@pytest.mark.parametrize("eps", [1.0, -0.25])
+@pytest.mark.parametrize("mu,colour", [(0, 0), (0, 3), (1, 2), (2, 1), (3, 0)])
+def test_single_pass_full_su3(eps, mu, colour):
+    """One annealing subset on a Haar-random field (every SU(3) entry non-zero).
+    rho is chosen so that the subset's links take both branches of the
+    Cayley-Hamilton coefficients (counted on the host from the oracle's Q)."""
+    dims = (8, 4, 8, 12)
+    U = _haar(dims, 100 + mu)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 11)
+    rho = 0.3 if eps == 1.0 else 0.16
+    small, large = _ch_branches(dims, U, mu, colour, rho, eps)
+    print(f"eps {eps} mu {mu} colour {colour}: {small} links on the series branch, {large} on the closed form")
+    assert small > 0 and large > 0
+    f = _field(dims)
+    f.set_charges(n)
+    api.set_links(f, torch.from_numpy(U))
+    api.anneal_pass(f, mu, colour, rho, eps)
     want = U.copy()
-    ora.anneal_pass(dims, want, n, mu, colour, rho=0.3, eps=eps)
-    assert np.abs(_links(f) - want).max() < 1e-13
+    ora.anneal_pass(dims, want, n, mu, colour, rho=rho, eps=eps)
+    err = np.abs(_links(f) - want).max()
+    print(f"  max link error {err:.2e}")
+    assert err < LINK_TOL
 
 
 def test_c0_jacobi_plain_stout():
@@ -187,18 +236,42 @@ def test_random_gauge_variant_full_su3(order):
     s = _stats(st, 3)
     np.testing.assert_array_equal(s.rejected, so.rejected)
     np.testing.assert_allclose(s.plaq, so.plaq, rtol=1e-12, atol=0)
+    # the measurement undoes the gauge too: vortex preservation keeps every flux
+    np.testing.assert_array_equal(s.flux_mismatch, so.flux_mismatch)
+    assert np.all(s.flux_mismatch == 0) and np.all(s.undefined_sector == 0)
     assert np.abs(_links(f) - U).max() < LINK_TOL
+
+
+def _as_stored(U):
+    """The field as the library holds it: rows 0 and 1, row 2 rebuilt as
+    conj(row0 x row1) (numpy), a rounding away from the exact SU(3) links."""
+    S = U.copy()
+    S[..., 2, :] = np.conj(np.cross(S[..., 0, :], S[..., 1, :]))
+    return S
+
+
+def _oracle_sensitivity(dims, U, n, want, **kw):
+    """How far the oracle's own result moves when its start is rounded as the
+    library stores it (same sweeps, kw as for ora.smooth): the amplification of a
+    rounding-level difference by the update, which bounds how closely two
+    correct FP64 implementations can agree.  Returns (sensitivity, result)."""
+    W = _as_stored(U)
+    ora.smooth(dims, W, n, measure_every=0, **kw)
+    return float(np.abs(W - want).max()), W
 
 
 @pytest.mark.parametrize("alpha,eps", [(1.0, 1.0), (0.7, -0.25), (0.02, -0.25)])
 def test_maxretr_annealed_random_gauge(alpha, eps):
     """MaxReTr (Sec. III): cooling (alpha = 1) and AUS (alpha = 0.7, 0.02) on a
-    random-gauge field, annealed, 3 subgroup loops."""
+    random-gauge field, annealed, 3 subgroup loops.  Bar: 1e-12, or ten times
+    the oracle's own sensitivity to the storage rounding of the start when that
+    is larger (an SU(2) hit with a small k divides by it, Sec. III)."""
     dims = (8, 8, 4, 8)
     n = fieldgen.z3_vortex_charges(dims, 0.1, 31)
     pairs = fieldgen.centrifuge_pairs(dims, 32)
     G = fieldgen.haar_su3(fieldgen.volume(dims), 33)
     U = ora.gauge_transform(dims, ora.centrifuge(dims, n, pairs, 0.02), G)
+    U0 = U.copy()
     f = _field(dims)
     f.set_charges(n)
     api.set_links(f, torch.from_numpy(U))
@@ -206,22 +279,29 @@ def test_maxretr_annealed_random_gauge(alpha, eps):
                     measure_every=1)
     so = ora.smooth(dims, U, n, 2, order="annealed", update="maxretr", alpha=alpha, eps=eps)
     np.testing.assert_allclose(_stats(st, 2).plaq, so.plaq, rtol=1e-12, atol=0)
-    assert np.abs(_links(f) - U).max() < 1e-11
+    err = np.abs(_links(f) - U).max()
+    sens, _ = _oracle_sensitivity(dims, U0, n, U, n_sweeps=2, order="annealed", update="maxretr", alpha=alpha,
+                                  eps=eps)
+    bar = max(LINK_TOL, 10.0 * sens)
+    print(f"maxretr alpha {alpha} eps {eps}: max link error {err:.2e}, oracle sensitivity {sens:.2e}, bar {bar:.1e}")
+    assert err < bar
 
 
 def test_centre_field_unchanged():
-    """Sec. II.A: a centre field has Q = 0 and is left unchanged by stout.  Row 2
-    of the stored link is rebuilt from rows 0 and 1, one rounding away from the
-    exact centre element, so Q is ~1e-15 instead of 0 and the field moves by
-    rounding only: within 1e-14 after five sweeps."""
+    """Sec. II.A: a centre field has Q = 0 and is left unchanged by stout, bit for
+    bit, annealed and smeared, plain and over-improved (a stored link's row 2,
+    rebuilt from rows 0 and 1, is a rounding away from the centre element; Q at
+    that rounding level counts as 0)."""
     dims = (8, 8, 8, 8)
     n = fieldgen.z3_vortex_charges(dims, 0.2, 41)
     f = _field(dims)
     api.load_z3(f, n)
     before = _links(f)
-    api.smooth(f, 3, 0.1, -0.25, order="annealed", vp=True)
+    st = _stats(api.smooth(f, 3, 0.1, -0.25, order="annealed", vp=True, measure_every=1), 3)
     api.smooth(f, 2, 0.1, 1.0, order="jacobi")
-    np.testing.assert_allclose(_links(f), before, atol=1e-14, rtol=0)
+    api.smooth(f, 2, 0.3, -0.25, order="jacobi")
+    np.testing.assert_array_equal(_links(f), before)
+    assert np.all(st.rejected == 0) and np.all(st.flux_mismatch == 0)
 
 
 def test_deterministic_and_resumable():
@@ -270,7 +350,11 @@ def test_vp_maxretr_leaves_a_z3_field_unchanged(dims, alpha):
     rejects all of them; the other links get updates that are the identity up to
     the rounding of the staple sums.  So the field after an annealed
     over-improved sweep is the original to rounding, the rejection count equals
-    the oracle's, and there are none below alpha_min."""
+    the oracle's, and there are none below alpha_min.  On the exact centre
+    field the oracle's hits are exact identities; the library stores row 2 of a
+    link rebuilt, a rounding away, and the hits amplify that by up to 1/k: the
+    oracle itself, started from the field as stored, moves by that much, and
+    the GPU's field must stay within ten times that (or 1e-12) of the oracle's."""
     n = fieldgen.z3_vortex_charges(dims, 0.1, 41)
     f = _field(dims)
     f.set_charges(n)
@@ -279,13 +363,18 @@ def test_vp_maxretr_leaves_a_z3_field_unchanged(dims, alpha):
     st = _stats(api.smooth(f, 1, 0.0, -0.25, order="annealed", update="maxretr", alpha=alpha, vp=True,
                            measure_every=1), 1)
     after = _links(f)
-    assert np.abs(after - before).max() < 1e-10
-    U = ora.z3_field(dims, n)
+    U0 = ora.z3_field(dims, n)
+    U = U0.copy()
     so = ora.smooth(dims, U, n, 1, order="annealed", update="maxretr", alpha=alpha, eps=-0.25, vp=True)
     assert int(st.rejected[0]) == int(so.rejected[0])
-    # where the staple sum nearly cancels v (|L^1| small) the SU(2) hit divides
-    # by a small k, which scales rounding differences up: 1e-10 here
-    assert np.abs(after - U).max() < 1e-10
+    sens, _ = _oracle_sensitivity(dims, U0, n, U, n_sweeps=1, order="annealed", update="maxretr", alpha=alpha,
+                                  eps=-0.25, vp=True)
+    bar = max(LINK_TOL, 10.0 * sens)
+    err = np.abs(after - U).max()
+    print(f"{dims} alpha {alpha}: max link error {err:.2e}, moved {np.abs(after - before).max():.2e}, "
+          f"oracle sensitivity {sens:.2e}, bar {bar:.1e}")
+    assert err < bar
+    assert np.abs(after - before).max() < bar
     if alpha < 0.4486:
         assert int(st.rejected[0]) == 0
     else:

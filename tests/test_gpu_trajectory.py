@@ -10,13 +10,14 @@ which is (1 - plaquette) up to normalisation and so cancels as the field
 smooths, within 1e-12 relative or 1e-13 absolute (its rounding error is set by
 the O(1) traces it is summed from, not by its own size); the rejection count
 of every sweep and the vortex flux (no mismatch) exact.  Links are compared at
-checkpoint sweeps: within 1e-12, or within ten times the oracle's own
-sensitivity at that sweep when that is larger (the fixture stores how far the
-oracle moves from a start perturbed at the rounding level; the accept/reject
-test and the flow near vortex cores amplify rounding differences, so after
-many sweeps two correct FP64 implementations differ by that much).  The
-FP32-bulk form is held to stated bounds on the action and link errors, with no
-vortex lost.
+checkpoint sweeps: within 1e-12 up to sweep 10 and within 1e-10 after that (the
+accept/reject test and the flow near vortex cores amplify rounding
+differences; the fixture stores how far the oracle itself moves from a start
+perturbed at the rounding level, a perturbation off the diagonal subgroup
+that the run itself never meets, so it overstates what two implementations on
+the diagonal subgroup drift apart and serves as context only).  The FP32-bulk
+form is held to stated bounds on the action and link errors, with no vortex
+lost.
 
 The 500 sweeps of the 32^3 x 64 workload (seeds 1002/2002, same recipe) are
 held to the FP64 bars against tests/golden/c2_oracle_trajectory.txt (written
@@ -100,7 +101,7 @@ def test_fp64_trajectory_matches_oracle():
     assert np.all(rec.nonfinite == 0) and np.all(rec.undefined_sector == 0)
     for k in sorted(links):
         err = _link_err(snaps[k], links[k])
-        bar = max(1e-12, 10.0 * sens[k])
+        bar = 1e-12 if k <= 10 else 1e-10
         print(f"sweep {k:3d}: link error {err:.2e}, oracle sensitivity {sens[k]:.2e}, bar {bar:.1e}")
         assert err <= bar, (k, err, bar)
 
