@@ -158,6 +158,26 @@ int vsm_smooth(const int32_t dims[4], int32_t precision, void *links_dev, const 
                int32_t n_sweeps, double rho, double eps, const vsm_schedule *sched,
                int32_t measure_every, vsm_stats *stats_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): vsm_smooth
+ * with every argument as there except the workspace, which is a static device
+ * array of VSM_NOALLOC_SCRATCH_BYTES (64 MiB) inside the library, one per device
+ * that the library runs on, held until the process ends.  The call allocates
+ * nothing; the caller still passes links, charges, gauge and stats.  Enough
+ * for annealed sweeps with measurement up to about 15.5M sites (48^3 x 96 fits)
+ * and for smearing up to 170k sites in FP64 (340k in FP32-bulk); larger
+ * lattices return VSM_E_WORKSPACE before anything is enqueued.  The first call
+ * on a device looks up that device's array (hipGetSymbolAddress) with the
+ * device current.  Every call on a device shares its array (counters, charges,
+ * reduction slots, the smearing buffer), and each call re-initialises what it
+ * reads: calls that overlap on one device (two streams, two threads) race and
+ * must be serialised by the caller. */
+#define VSM_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+size_t vsm_noalloc_scratch_bytes(void);
+int vsm_smooth_noalloc(const int32_t dims[4], int32_t precision, void *links_dev, const int8_t *z3_dev,
+                       const double *gauge_dev, int32_t n_sweeps, double rho, double eps,
+                       const vsm_schedule *sched, int32_t measure_every, vsm_stats *stats_dev, void *stream);
+
 /* One annealing subset (direction mu, subset colour) of the update chosen by
  * *sched, in place; the building block of an annealed sweep.  The rejection
  * count accumulates in the workspace until the next measurement. */

@@ -89,6 +89,9 @@ SIGNATURES = {
     "vsm_pass": (ctypes.c_int, [Dims, _i32, _P, _P, _P, _P, _sz, _i32, _i32, _f64, _f64,
                                 ctypes.POINTER(Schedule), _P]),
     "vsm_measure": (ctypes.c_int, [Dims, _i32, _P, _P, _P, _P, _sz, _P, _P, _P]),
+    "vsm_noalloc_scratch_bytes": (_sz, []),
+    "vsm_smooth_noalloc": (ctypes.c_int, [Dims, _i32, _P, _P, _P, _i32, _f64, _f64, ctypes.POINTER(Schedule),
+                                          _i32, _P, _P]),
 }
 
 _lib = None

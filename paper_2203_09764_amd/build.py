@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libvsm.so")
-SOURCES = ["vsm_k_f64.hip", "vsm_k_f32.hip", "vsm_kernels.hip", "vsm_api.hip", "vsm_server.hip"]
+SOURCES = ["vsm_k_f64.hip", "vsm_k_f32.hip", "vsm_kernels.hip", "vsm_api.hip", "vsm_server.hip",
+           "vsm_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"),
          "-I" + CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -170,3 +170,25 @@ def test_server_create_validates_config():
     assert lib().vsm_server_create(None, ctypes.byref(h)) == E_NULL
     assert lib().vsm_server_submit(None, None, None) == E_NULL
     assert E_BUDGET < 0
+
+
+def test_noalloc_checks_before_any_hip_call():
+    """vsm_smooth_noalloc validates and refuses a lattice whose workspace exceeds
+    its static scratch (VSM_E_WORKSPACE) before touching the GPU."""
+    assert lib().vsm_noalloc_scratch_bytes() == 64 << 20
+    sched = Schedule(JACOBI, STOUT, 0, 3, 1.0, 1.0)
+    p = ctypes.c_void_p(16)
+    # smearing needs a second link buffer: 384 MiB in FP64 at 32^4
+    rc = lib().vsm_smooth_noalloc(dims_arg((32, 32, 32, 32)), FP64, p, p, None, 1, 0.1, 1.0, ctypes.byref(sched),
+                                  0, None, None)
+    assert rc == E_WORKSPACE
+    ann = Schedule(ANNEALED, STOUT, 1, 3, 1.0, 1.0)
+    # annealed: 4V charge bytes and the reduction slots; 48^3 x 200 (22M sites) is too large in FP32
+    rc = lib().vsm_smooth_noalloc(dims_arg((48, 48, 48, 200)), FP32_BULK, p, p, None, 1, 0.1, 1.0,
+                                  ctypes.byref(ann), 1, p, None)
+    assert rc == E_WORKSPACE
+    assert lib().vsm_smooth_noalloc(dims_arg((8, 8, 6, 8)), FP64, p, p, None, 1, 0.1, 1.0, ctypes.byref(ann), 0,
+                                    None, None) == E_DIMS
+    assert lib().vsm_smooth_noalloc(dims_arg((8, 8, 8, 8)), FP64, p, p, None, 1, 0.1, 1.0, None, 0, None,
+                                    None) == E_NULL
+
