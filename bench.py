@@ -9,8 +9,11 @@ one such sweep: 16 subset passes over all 4V links plus the measurement.
 Prints ONE JSON line.  value = link updates per second (4V per sweep) of the
 whole timed region (inputs resident in HBM, K sweeps, both ends synchronised).
 roofline = the dominant kernel (one annealing subset pass) against HBM
-bandwidth: algorithmic bytes per launch / the average launch duration measured
-with HIP events on the library's stream.  cpu_baseline = the FP64 CPU oracle
+bandwidth: algorithmic bytes per launch (every link read once and the updated
+one written, counted as full 3x3 complex matrices, plus its charge byte) / the
+average launch duration measured with HIP events on the library's stream; the
+fraction by the bytes this layout moves (rows 0 and 1 of each link) is given
+beside it.  cpu_baseline = the FP64 CPU oracle
 timed on a bounded sample (the first subset passes of the same field, ~10 s).
 """
 from __future__ import annotations
@@ -37,13 +40,18 @@ WORKLOADS = {
 }
 
 
-def pass_bytes_per_lu(precision: str) -> int:
+def pass_bytes_per_lu(precision: str, stored: bool = False) -> int:
     """Algorithmic HBM bytes per link update of one annealing subset pass: the
     pass reads every link of the lattice once (4V links for V/4 updates = 16 per
     update), writes the updated link, and reads its original charge (1 byte).
-    A stored link is its rows 0 and 1: 6 complex entries, 96 B in FP64 and 48 B
-    in FP32 (row 2 is rebuilt in registers)."""
-    link = 96 if precision == "fp64" else 48
+    A link counts as a full 3x3 complex matrix, 144 B in FP64 and 72 B in FP32
+    (2449 and 1225 B per update).  With stored=True the count uses what this
+    library's layout moves: rows 0 and 1, 96 B in FP64 and 48 B in FP32 (row 2
+    is rebuilt in registers), 1633 and 817 B per update."""
+    if stored:
+        link = 96 if precision == "fp64" else 48
+    else:
+        link = 144 if precision == "fp64" else 72
     return 16 * link + link + 1
 
 
@@ -125,10 +133,12 @@ def run_gpu_form(args, precision, dims, n, pairs):
     launch_lu = V // 4
     algo_bytes = launch_lu * pass_bytes_per_lu(precision)
     achieved = algo_bytes / (avg_pass_ms * 1e-3) / 1e9
+    stored_bytes = launch_lu * pass_bytes_per_lu(precision, stored=True)
     return dict(
         precision=precision, ms=ms, wall_s=wall, lu_per_s=lu / (ms * 1e-3),
         ms_per_step=ms / args.steps, avg_pass_ms=avg_pass_ms, pass_launch_lu=launch_lu,
-        pass_algo_bytes=algo_bytes, achieved_gbs=achieved,
+        pass_algo_bytes=algo_bytes, achieved_gbs=achieved, pass_stored_bytes=stored_bytes,
+        achieved_stored_gbs=stored_bytes / (avg_pass_ms * 1e-3) / 1e9,
         action=[float(a) for a in st.action], plaq_last=float(st.plaq[-1]),
         flux_mismatch=int(st.flux_mismatch.sum()), nonfinite=int(st.nonfinite.sum()),
         max_unitarity=float(st.max_unitarity.max()), rejected=int(st.rejected.sum()),
@@ -220,12 +230,9 @@ def flow_form(dims, n, pairs, precision, steps=2, eps=0.02):
             "ms_per_step": round(ms, 3), "link_updates_per_s": round(3 * 4 * f.V / (ms * 1e-3), 1)}
 
 
-def serving_leg(n_jobs: int, rate: float, slots: int = 64, seed: int = 3):
-    """The serving stream: Poisson arrivals at `rate` jobs/s of smoothing jobs on
-    8^4, 12^3x24, 16^3x32 and 20^3x40 vortex fields (p uniform in [0.05, 0.15],
-    50-300 sweeps), FP32-bulk annealed over-improved stout with vortex
-    preservation, one final measurement each.  Inputs are generated before the
-    clock starts; latency = completion - submission on the server's clock."""
+def _serve_stream(n_jobs: int, rate: float, slots: int, seed: int) -> dict:
+    """One replay of a Poisson stream of `n_jobs` jobs at `rate` jobs/s against a
+    fresh server; inputs are generated before the clock starts."""
     import fieldgen
     from paper_2203_09764_amd import serve
 
@@ -239,16 +246,43 @@ def serving_leg(n_jobs: int, rate: float, slots: int = 64, seed: int = 3):
                       max_inflight=4) as srv:
         r = serve.run_stream(srv, jobs, precision="fp32_bulk", measure_every=0, rho=0.06, eps=-0.25,
                              vp=True, omega=0.02, timeout=600)
-    lost = sum(int(rec.flux_mismatch[-1]) for rec in r["records"])
+    r["offered_lu_per_s"] = r["link_updates"] / (specs[-1].arrival_s or 1.0)
+    r["lost"] = sum(int(rec.flux_mismatch[-1]) for rec in r["records"])
+    return r
+
+
+def serving_leg(n_jobs: int, rate: float, slots: int = 64, seed: int = 3,
+                loads=((0.5, 120), (0.8, 150), (1.0, 150))):
+    """The serving stream: Poisson arrivals at `rate` jobs/s of smoothing jobs on
+    8^4, 12^3x24, 16^3x32 and 20^3x40 vortex fields (p uniform in [0.05, 0.15],
+    50-300 sweeps), FP32-bulk annealed over-improved stout with vortex
+    preservation, one final measurement each.  Latency = completion - submission
+    on the server's clock.  The configured stream overloads the GPU, so its
+    served rate is the capacity; the stream is then replayed at fractions of that
+    capacity (other arrival seeds, `loads` = (fraction, jobs)) for the
+    latency-versus-load curve."""
+    r = _serve_stream(n_jobs, rate, slots, seed)
     c = r["counters"]
-    return {"workload": "Poisson stream, mean %g jobs/s, %d jobs on 8^4 / 12^3x24 / 16^3x32 / 20^3x40 "
-                        "vortex fields, 50-300 sweeps each, FP32-bulk annealed OI stout + VP" % (rate, n_jobs),
-            "p50_latency_s": round(r["p50_s"], 4), "p99_latency_s": round(r["p99_s"], 4),
-            "mean_queue_s": round(r["mean_queue_s"], 4), "lu_per_s": round(r["lu_per_s"], 1),
-            "offered_lu_per_s": round(r["link_updates"] / (specs[-1].arrival_s or 1.0), 1),
-            "span_s": round(r["span_s"], 3), "steps": int(c["steps"]), "launches": int(c["launches"]),
-            "peak_resident_jobs": int(c["peak_resident_jobs"]),
-            "peak_pool_mib": round(c["peak_pool_bytes"] / 2**20, 1), "flux_mismatch_total": lost}
+    mean_job_lu = r["link_updates"] / r["n_jobs"]
+    capacity = r["lu_per_s"] / mean_job_lu
+    out = {"workload": "Poisson stream, mean %g jobs/s, %d jobs on 8^4 / 12^3x24 / 16^3x32 / 20^3x40 "
+                       "vortex fields, 50-300 sweeps each, FP32-bulk annealed OI stout + VP" % (rate, n_jobs),
+           "p50_latency_s": round(r["p50_s"], 4), "p99_latency_s": round(r["p99_s"], 4),
+           "mean_queue_s": round(r["mean_queue_s"], 4), "lu_per_s": round(r["lu_per_s"], 1),
+           "offered_lu_per_s": round(r["offered_lu_per_s"], 1),
+           "span_s": round(r["span_s"], 3), "steps": int(c["steps"]), "launches": int(c["launches"]),
+           "peak_resident_jobs": int(c["peak_resident_jobs"]),
+           "peak_pool_mib": round(c["peak_pool_bytes"] / 2**20, 1), "flux_mismatch_total": r["lost"],
+           "capacity_jobs_per_s": round(capacity, 2)}
+    curve = []
+    for k, (frac, nj) in enumerate(loads):
+        q = _serve_stream(nj, frac * capacity, slots, seed + 10 + k)
+        curve.append({"load": frac, "rate_jobs_per_s": round(frac * capacity, 2), "n_jobs": nj,
+                      "p50_latency_s": round(q["p50_s"], 4), "p99_latency_s": round(q["p99_s"], 4),
+                      "mean_queue_s": round(q["mean_queue_s"], 4), "lu_per_s": round(q["lu_per_s"], 1),
+                      "offered_lu_per_s": round(q["offered_lu_per_s"], 1), "flux_mismatch_total": q["lost"]})
+    out["latency_vs_load"] = curve
+    return out
 
 
 def cpu_baseline(dims, n, pairs, threads):
@@ -348,6 +382,9 @@ def main():
             "traffic": traffic,
             "kernel": f"k_update annealed OI stout pass ({hp})",
             "algorithmic_bytes_per_launch": head["pass_algo_bytes"],
+            "algorithmic_bytes_per_lu": pass_bytes_per_lu(hp),
+            "stored_bytes_per_lu": pass_bytes_per_lu(hp, stored=True),
+            "frac_stored_bytes": round(head["achieved_stored_gbs"] / HBM_PEAK_GBS, 4),
             "avg_launch_ms": round(head["avg_pass_ms"], 4),
             "stream_read_gbs": round(read_gbs, 1),
             "frac_of_stream_read": round(head["achieved_gbs"] / read_gbs, 4)}
@@ -369,6 +406,7 @@ def main():
         forms_out[p] = {"lu_per_s": round(r["lu_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                         "avg_pass_ms": round(r["avg_pass_ms"], 4),
                         "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                        "hbm_frac_stored_bytes": round(r["achieved_stored_gbs"] / HBM_PEAK_GBS, 4),
                         "flux_mismatch": r["flux_mismatch"], "nonfinite": r["nonfinite"],
                         "max_unitarity": r["max_unitarity"], "final_action": r["action"][-1],
                         "clover_measure": r["clover"]}

@@ -13,6 +13,7 @@ template void launch_update_t<float>(const Geo&, const void*, void*, const int8_
 template void launch_measure_t<float>(const Geo&, const void*, const int8_t*, const void*, void*, int8_t*,
                                   unsigned long long*, VsmStatsDev*, long long, hipStream_t);
 template void launch_update_batch_t<float>(const ServeJob*, const BatchStep&, uint32_t, hipStream_t);
+template void launch_serve_small_t<float>(const ServeJob*, const SmallStep&, hipStream_t);
 template void launch_clover_t<float>(const Geo&, const void*, void*, double*, double*, double*, hipStream_t);
 template void launch_flow_t<float>(const Geo&, const void*, void*, double*, int, double, double, double, hipStream_t);
 }  // namespace vsm

@@ -20,6 +20,8 @@ void launch_update_t(const Geo&, const void*, void*, const int8_t*, const void*,
 template <typename R>
 void launch_update_batch_t(const ServeJob*, const BatchStep&, uint32_t, hipStream_t);
 template <typename R>
+void launch_serve_small_t(const ServeJob*, const SmallStep&, hipStream_t);
+template <typename R>
 void launch_clover_t(const Geo&, const void*, void*, double*, double*, double*, hipStream_t);
 template <typename R>
 void launch_flow_t(const Geo&, const void*, void*, double*, int, double, double, double, hipStream_t);
@@ -95,6 +97,11 @@ void launch_update_batch(int prec, const ServeJob* jobs_dev, const BatchStep& st
                          hipStream_t st) {
   if (prec == 0) launch_update_batch_t<double>(jobs_dev, step, nblocks, st);
   else launch_update_batch_t<float>(jobs_dev, step, nblocks, st);
+}
+
+void launch_serve_small(int prec, const ServeJob* jobs_dev, const SmallStep& step, hipStream_t st) {
+  if (prec == 0) launch_serve_small_t<double>(jobs_dev, step, st);
+  else launch_serve_small_t<float>(jobs_dev, step, st);
 }
 
 void launch_flow(int prec, const Geo& g, const void* src, void* dst, double* acc, int stage, double eps,

@@ -719,6 +719,54 @@ __global__ void __launch_bounds__(256) k_update_batch(const ServeJob* __restrict
   if ((threadIdx.x & 63u) == 0u && m) atomicAdd(J.rej, (unsigned long long)__popcll(m));
 }
 
+// Small-lattice serving step (see SmallStep): workgroup b runs sweeps[b] whole
+// annealed sweeps of job slot[b] -- for mu = 0..3 (user order), subsets 0, 2,
+// 1, 3, each pass over all V/4 links of the subset with the per-link code of
+// k_update (batch_one), its threads striding over the subset -- with a
+// workgroup barrier after every pass, so the next pass reads the links this one
+// stored (all waves of a workgroup share one CU and its L1).  No device-wide
+// wait: the job lives in one workgroup.  Rejections are counted per wave into
+// the job's counter.
+template <typename R>
+__global__ void __launch_bounds__(256) k_serve_small(const ServeJob* __restrict__ jobs, SmallStep st) {
+  if (blockIdx.x >= st.njobs) return;
+  const ServeJob& J = jobs[st.slot[blockIdx.x]];
+  const int nsw = st.sweeps[blockIdx.x];
+  const uint32_t V4 = J.g.V4;
+  unsigned long long rej = 0;
+  for (int sw = 0; sw < nsw; ++sw) {
+    for (int d = 0; d < 4; ++d) {
+      const int mu = J.g.perm[d];
+      for (int k = 0; k < 4; ++k) {
+        const int colour = k == 1 ? 2 : (k == 2 ? 1 : k);
+        for (uint32_t t0 = 0; t0 < V4; t0 += blockDim.x) {
+          const uint32_t t = t0 + threadIdx.x;
+          bool r;
+          if (J.p.oi) {
+            switch (mu) {
+              case 0: r = batch_one<R, 0, true>(J, colour, t); break;
+              case 1: r = batch_one<R, 1, true>(J, colour, t); break;
+              case 2: r = batch_one<R, 2, true>(J, colour, t); break;
+              default: r = batch_one<R, 3, true>(J, colour, t); break;
+            }
+          } else {
+            switch (mu) {
+              case 0: r = batch_one<R, 0, false>(J, colour, t); break;
+              case 1: r = batch_one<R, 1, false>(J, colour, t); break;
+              case 2: r = batch_one<R, 2, false>(J, colour, t); break;
+              default: r = batch_one<R, 3, false>(J, colour, t); break;
+            }
+          }
+          rej += r ? 1ull : 0ull;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) rej += __shfl_xor(rej, off);
+  if ((threadIdx.x & 63u) == 0u && rej) atomicAdd(J.rej, rej);
+}
+
 // ------------------------------------------------------------------ Wilson flow
 
 // One stage of the Wilson flow (Sec. II.B, V.B) for every link of direction MU,
@@ -1289,6 +1337,12 @@ void launch_update_batch_t(const ServeJob* jobs, const BatchStep& step, uint32_t
   const unsigned lds = sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u;
   const uint32_t nb8 = (nblocks + 7u) & ~7u;
   hipLaunchKernelGGL(k_update_batch<R>, dim3(nb8), dim3(256), lds, st, jobs, step);
+}
+
+template <typename R>
+void launch_serve_small_t(const ServeJob* jobs, const SmallStep& step, hipStream_t st) {
+  if (step.njobs == 0) return;
+  hipLaunchKernelGGL(k_serve_small<R>, dim3(step.njobs), dim3(256), 0, st, jobs, step);
 }
 
 template <typename R, int MU>

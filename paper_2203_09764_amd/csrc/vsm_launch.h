@@ -51,6 +51,21 @@ struct BatchStep {
   uint32_t njobs;
 };
 
+// One step of the small-lattice serving path: each listed job runs `sweeps[i]`
+// whole annealed sweeps (all 16 subset passes of each) inside one workgroup,
+// the passes separated by workgroup barriers; job i is jobs[slot[i]].
+constexpr int kSmallMax = 128;
+struct SmallStep {
+  uint16_t slot[kSmallMax];
+  uint16_t sweeps[kSmallMax];
+  uint32_t njobs;
+};
+// Lattices of at most this many sites are served by the small-lattice path: a
+// workgroup of 256 threads then takes at most 8 rounds per subset pass, faster
+// than a pass per batched step; larger lattices are faster spread over many
+// workgroups, one pass per step.
+constexpr uint32_t kSmallSites = 8192;
+
 void launch_set_links(int prec, const Geo& g, const void* canon, void* links, hipStream_t st);
 void launch_get_links(int prec, const Geo& g, const void* links, void* canon, hipStream_t st);
 void launch_load_z3(int prec, const Geo& g, const int8_t* z3, void* links, hipStream_t st);
@@ -72,6 +87,9 @@ inline uint32_t pass_blocks(const Geo& g) { return (g.V4 + 255u) / 256u; }
 // One serving step: every job of `step` (stout updates, annealed, in place).
 void launch_update_batch(int prec, const ServeJob* jobs_dev, const BatchStep& step, uint32_t nblocks,
                          hipStream_t st);
+// One small-lattice serving step (stout updates, annealed, in place), one
+// workgroup per job of `step`.
+void launch_serve_small(int prec, const ServeJob* jobs_dev, const SmallStep& step, hipStream_t st);
 // Charges z3 (canonical layout) into out (internal layout, 4V bytes) for the
 // internal directions d0 .. d0 + nd - 1.
 void launch_charges(const Geo& g, const int8_t* z3, int8_t* out, int d0, int nd, hipStream_t st);

@@ -1,7 +1,10 @@
 // vsm_server.hip -- the serving scheduler of include/vsm.h: a FIFO of smoothing
 // jobs admitted by memory footprint into resident slots, and a worker thread
-// that advances every resident job by one annealing subset pass per step, all
-// jobs of a step in one batched launch.
+// that drives two streams.  Lattices above kSmallSites advance by one annealing
+// subset pass per step, all such jobs of a step in one batched launch; small
+// lattices advance by whole sweeps per step, each job inside one workgroup of a
+// persistent launch (k_serve_small) on a second stream, so that their many
+// short passes neither cost a launch each nor wait for the large jobs' steps.
 #include <string.h>
 
 #include <chrono>
@@ -137,6 +140,8 @@ struct Job {
   int state = VSM_JOB_QUEUED, status = VSM_OK;
   int n_records = 0, rec = 0;
   int64_t pass = 0, n_pass = 0;
+  bool small = false;      // served by the small-lattice path
+  hipStream_t st = nullptr;  // the stream all of the job's device work goes to
   double t_submit = -1, t_admit = -1, t_done = -1;
   hipEvent_t done_ev = nullptr;
   char* dbase = nullptr;
@@ -146,18 +151,19 @@ struct Job {
 class Server {
  public:
   vsm_server_config cfg{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;        // large lattices: batched pass steps
+  hipStream_t stream_small = nullptr;  // small lattices: whole-sweep workgroup steps
   char* dev_pool = nullptr;
   char* host_pool = nullptr;
   ServeJob* jobs_dev = nullptr;
   ServeJob* desc_host = nullptr;  // pinned staging of the job descriptors, one per slot
-  std::vector<hipEvent_t> step_ev;
+  std::vector<hipEvent_t> step_ev, small_ev;
   std::unique_ptr<Arena> dev_arena, host_arena;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
-  std::deque<Job*> queue, running, finishing;
+  std::deque<Job*> queue, running, running_small, finishing;
   std::vector<int> free_slots;
   uint64_t next_id = 1;
   uint64_t gen = 0;  // bumped by submit and fetch: the queue head may now fit
@@ -195,7 +201,7 @@ class Server {
     const WsLayout w = ws_layout(j->desc.dims, j->desc.precision, VSM_ANNEALED);
     launch_measure(j->desc.precision, j->g, d + j->lay.links, (const int8_t*)(d + j->lay.ws + w.charges),
                    nullptr, d + j->lay.ws + w.partials, nullptr, (unsigned long long*)(d + j->lay.ws),
-                   (VsmStatsDev*)(d + j->lay.records) + j->rec, sweep, stream);
+                   (VsmStatsDev*)(d + j->lay.records) + j->rec, sweep, j->st);
     ++j->rec;
     ++ctr.launches;
     return hip_status();
@@ -208,19 +214,19 @@ class Server {
     if (j->rec < j->n_records) rc = enqueue_measure(j, j->desc.n_sweeps);
     char* d = j->dbase;
     if (!rc && j->desc.want_links) {
-      launch_get_links(j->desc.precision, j->g, d + j->lay.links, d + j->lay.canon, stream);
+      launch_get_links(j->desc.precision, j->g, d + j->lay.links, d + j->lay.canon, j->st);
       ++ctr.launches;
       rc = hip_status();
     }
     hipError_t e = hipSuccess;
     if (!rc && j->n_records > 0)
       e = hipMemcpyAsync(j->hbase + j->lay.h_records, d + j->lay.records,
-                         (size_t)j->n_records * sizeof(vsm_stats), hipMemcpyDeviceToHost, stream);
+                         (size_t)j->n_records * sizeof(vsm_stats), hipMemcpyDeviceToHost, j->st);
     if (!rc && e == hipSuccess && j->desc.want_links)
       e = hipMemcpyAsync(j->hbase + j->lay.h_links, d + j->lay.canon, 4ull * j->g.V * 9 * 16,
-                         hipMemcpyDeviceToHost, stream);
+                         hipMemcpyDeviceToHost, j->st);
     if (!rc && e == hipSuccess) e = hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming);
-    if (!rc && e == hipSuccess) e = hipEventRecord(j->done_ev, stream);
+    if (!rc && e == hipSuccess) e = hipEventRecord(j->done_ev, j->st);
     if (!rc && e != hipSuccess) rc = note_hip_error(e);
     return rc;
   }
@@ -245,7 +251,10 @@ class Server {
       free_slots.pop_back();
       j->state = VSM_JOB_RUNNING;
       j->t_admit = now();
-      running.push_back(j);
+      j->small = j->g.V <= kSmallSites;
+      j->st = j->small ? stream_small : stream;
+      (j->small ? running_small : running).push_back(j);
+      hipStream_t st = j->st;
       const size_t V = j->g.V;
       char* d = j->dbase;
       memcpy(j->hbase + j->lay.h_in_z3, j->z3.data(), 4 * V);
@@ -262,29 +271,28 @@ class Server {
       // previous job has completed on the device
       desc_host[j->slot] = sj;
       hipError_t e = hipMemcpyAsync(jobs_dev + j->slot, desc_host + j->slot, sizeof(ServeJob),
-                                    hipMemcpyHostToDevice, stream);
+                                    hipMemcpyHostToDevice, st);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(d + j->lay.z3, j->hbase + j->lay.h_in_z3, 4 * V, hipMemcpyHostToDevice, stream);
+        e = hipMemcpyAsync(d + j->lay.z3, j->hbase + j->lay.h_in_z3, 4 * V, hipMemcpyHostToDevice, st);
       if (e == hipSuccess && j->desc.pair_host)
-        e = hipMemcpyAsync(d + j->lay.pairs, j->hbase + j->lay.h_in_pairs, 4 * V, hipMemcpyHostToDevice,
-                           stream);
+        e = hipMemcpyAsync(d + j->lay.pairs, j->hbase + j->lay.h_in_pairs, 4 * V, hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return note_hip_error(e);
       if (j->desc.pair_host)
         launch_centrifuge(j->desc.precision, j->g, (const int8_t*)(d + j->lay.z3),
-                          (const int8_t*)(d + j->lay.pairs), j->desc.omega, d + j->lay.links, nullptr, stream);
+                          (const int8_t*)(d + j->lay.pairs), j->desc.omega, d + j->lay.links, nullptr, st);
       else
-        launch_load_z3(j->desc.precision, j->g, (const int8_t*)(d + j->lay.z3), d + j->lay.links, stream);
+        launch_load_z3(j->desc.precision, j->g, (const int8_t*)(d + j->lay.z3), d + j->lay.links, st);
       launch_charges(j->g, (const int8_t*)(d + j->lay.z3),
                      (int8_t*)(d + j->lay.ws + ws_layout(j->desc.dims, j->desc.precision, VSM_ANNEALED).charges), 0,
-                     4, stream);
-      launch_zero_u64((unsigned long long*)(d + j->lay.ws), 1, stream);
+                     4, st);
+      launch_zero_u64((unsigned long long*)(d + j->lay.ws), 1, st);
       ctr.launches += 3;
       int rc = hip_status();
       if (rc) return rc;
-      const int64_t resident = (int64_t)(running.size() + finishing.size());
+      const int64_t resident = (int64_t)(running.size() + running_small.size() + finishing.size());
       if (resident > ctr.peak_resident_jobs) ctr.peak_resident_jobs = resident;
       if (j->n_pass == 0) {
-        running.pop_back();
+        (j->small ? running_small : running).pop_back();
         rc = enqueue_finish(j);
         if (rc) return rc;
         finishing.push_back(j);
@@ -355,6 +363,75 @@ class Server {
     return VSM_OK;
   }
 
+  // One small-lattice step: every running small job advances by whole sweeps
+  // inside one workgroup (k_serve_small), about kSmallStepSites sites' worth of
+  // sweeps each, so that a step costs about the same for every job; a step
+  // stops at the job's next measurement and at its last sweep.
+  static constexpr int64_t kSmallStepSites = 32768;
+
+  int small_step() {
+    std::vector<Job*> order(running_small.begin(), running_small.end());
+    std::vector<int> nsw(order.size(), 0);
+    for (size_t i = 0; i < order.size(); ++i) {
+      Job* j = order[i];
+      const int done = (int)(j->pass / 16), total = j->desc.n_sweeps;
+      int c = (int)(kSmallStepSites / (int64_t)j->g.V);
+      if (c < 1) c = 1;
+      if (c > total - done) c = total - done;
+      const int me = j->desc.measure_every;
+      if (me > 0 && c > me - done % me) c = me - done % me;
+      nsw[i] = c;
+    }
+    for (int prec = 0; prec < 2; ++prec) {
+      SmallStep ss;
+      memset(&ss, 0, sizeof(ss));
+      auto flush = [&]() -> int {
+        if (ss.njobs == 0) return VSM_OK;
+        launch_serve_small(prec, jobs_dev, ss, stream_small);
+        ++ctr.launches;
+        memset(&ss, 0, sizeof(ss));
+        return hip_status();
+      };
+      for (size_t i = 0; i < order.size(); ++i) {
+        Job* j = order[i];
+        if (j->desc.precision != prec) continue;
+        ss.slot[ss.njobs] = (uint16_t)j->slot;
+        ss.sweeps[ss.njobs] = (uint16_t)nsw[i];
+        ++ss.njobs;
+        ctr.link_updates += 4ll * j->g.V * nsw[i];
+        if (ss.njobs == (uint32_t)kSmallMax) {
+          const int rc = flush();
+          if (rc) return rc;
+        }
+      }
+      const int rc = flush();
+      if (rc) return rc;
+    }
+    for (size_t i = 0; i < order.size(); ++i) {
+      Job* j = order[i];
+      j->pass += 16ll * nsw[i];
+      const int sw = (int)(j->pass / 16);
+      if (j->desc.measure_every > 0 && sw % j->desc.measure_every == 0) {
+        const int rc = enqueue_measure(j, sw);
+        if (rc) return rc;
+      }
+      if (j->pass == j->n_pass) {
+        const int rc = enqueue_finish(j);
+        if (rc) return rc;
+      }
+    }
+    for (auto it = running_small.begin(); it != running_small.end();) {
+      if ((*it)->pass == (*it)->n_pass) {
+        finishing.push_back(*it);
+        it = running_small.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    ++ctr.steps;
+    return VSM_OK;
+  }
+
   // Moves finishing jobs whose results have reached the host to DONE.
   void retire() {
     for (auto it = finishing.begin(); it != finishing.end();) {
@@ -380,11 +457,17 @@ class Server {
   void break_all(int rc) {
     broken = rc;
     (void)hipStreamSynchronize(stream);
+    (void)hipStreamSynchronize(stream_small);
     for (Job* j : running) {
       fail_job(j, rc);
       release_device(j);
     }
     running.clear();
+    for (Job* j : running_small) {
+      fail_job(j, rc);
+      release_device(j);
+    }
+    running_small.clear();
     for (Job* j : finishing) {
       fail_job(j, rc);
       release_device(j);
@@ -401,8 +484,18 @@ class Server {
       const hipError_t e = hipSetDevice(cfg.device);
       if (e != hipSuccess) break_all(note_hip_error(e));
     }
-    int64_t nstep = 0;
+    int64_t nstep = 0, nsmall = 0;
     double busy_from = -1;
+    // a stream may take its next step when fewer than max_inflight of its steps
+    // are still queued on the device (*err: a failed query)
+    auto room = [&](const std::vector<hipEvent_t>& ev, int64_t n, int* err) -> bool {
+      *err = VSM_OK;
+      if (n < cfg.max_inflight) return true;
+      const hipError_t e = hipEventQuery(ev[n % cfg.max_inflight]);
+      if (e == hipErrorNotReady) return false;
+      if (e != hipSuccess) *err = note_hip_error(e);
+      return e == hipSuccess;
+    };
     for (;;) {
       const uint64_t seen = gen;
       retire();
@@ -413,13 +506,13 @@ class Server {
           continue;
         }
       }
-      const bool resident = !running.empty() || !finishing.empty();
+      const bool resident = !running.empty() || !running_small.empty() || !finishing.empty();
       if (resident && busy_from < 0) busy_from = now();
       if (!resident && busy_from >= 0) {
         ctr.busy_seconds += now() - busy_from;
         busy_from = -1;
       }
-      if (running.empty()) {
+      if (running.empty() && running_small.empty()) {
         if (!finishing.empty()) {
           hipEvent_t ev = finishing.front()->done_ev;
           lk.unlock();
@@ -433,30 +526,54 @@ class Server {
         continue;
       }
       if (stopping) break;
-      // at most max_inflight steps ahead of the device
-      if (nstep >= cfg.max_inflight) {
-        hipEvent_t ev = step_ev[nstep % cfg.max_inflight];
-        lk.unlock();
-        const hipError_t e = hipEventSynchronize(ev);
-        lk.lock();
-        if (e != hipSuccess) {
-          break_all(note_hip_error(e));
+      bool progressed = false;
+      int err = VSM_OK;
+      if (!running.empty()) {
+        const bool r = room(step_ev, nstep, &err);
+        if (err) {
+          break_all(err);
           continue;
         }
-        retire();
+        if (r) {
+          int rc = step();
+          if (!rc) rc = note_hip_error(hipEventRecord(step_ev[nstep % cfg.max_inflight], stream));
+          if (rc) {
+            break_all(rc);
+            continue;
+          }
+          ++nstep;
+          progressed = true;
+        }
       }
-      int rc = step();
-      if (!rc) rc = note_hip_error(hipEventRecord(step_ev[nstep % cfg.max_inflight], stream));
-      if (rc) {
-        break_all(rc);
-        continue;
+      if (!running_small.empty()) {
+        const bool r = room(small_ev, nsmall, &err);
+        if (err) {
+          break_all(err);
+          continue;
+        }
+        if (r) {
+          int rc = small_step();
+          if (!rc) rc = note_hip_error(hipEventRecord(small_ev[nsmall % cfg.max_inflight], stream_small));
+          if (rc) {
+            break_all(rc);
+            continue;
+          }
+          ++nsmall;
+          progressed = true;
+        }
       }
-      ++nstep;
+      if (!progressed) {
+        // both streams have max_inflight steps queued: let the device catch up
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        lk.lock();
+      }
     }
     if (busy_from >= 0) ctr.busy_seconds += now() - busy_from;
     // shutdown: let the device finish, keep what completed, fail the rest
     lk.unlock();
     (void)hipStreamSynchronize(stream);
+    (void)hipStreamSynchronize(stream_small);
     lk.lock();
     retire();
     for (Job* j : finishing) {
@@ -469,6 +586,11 @@ class Server {
       release_device(j);
     }
     running.clear();
+    for (Job* j : running_small) {
+      fail_job(j, VSM_E_STATE);
+      release_device(j);
+    }
+    running_small.clear();
     for (Job* j : queue) fail_job(j, VSM_E_STATE);
     queue.clear();
     cv_done.notify_all();
@@ -488,7 +610,9 @@ class Server {
 
 void free_server(Server* s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->stream_small) (void)hipStreamSynchronize(s->stream_small);
   for (hipEvent_t e : s->step_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s->small_ev) (void)hipEventDestroy(e);
   for (auto& kv : s->jobs)
     if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
   if (s->dev_pool) (void)hipFree(s->dev_pool);
@@ -496,6 +620,7 @@ void free_server(Server* s) {
   if (s->host_pool) (void)hipHostFree(s->host_pool);
   if (s->desc_host) (void)hipHostFree(s->desc_host);
   if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->stream_small) (void)hipStreamDestroy(s->stream_small);
   delete s;
 }
 
@@ -524,6 +649,7 @@ int vsm_server_create(const vsm_server_config* cfg, void** srv) {
   s->t0 = std::chrono::steady_clock::now();
   hipError_t e = hipSetDevice(cfg->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream_small, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc((void**)&s->dev_pool, cfg->hbm_budget_bytes);
   if (e == hipSuccess) e = hipMalloc((void**)&s->jobs_dev, sizeof(ServeJob) * (size_t)cfg->max_slots);
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_pool, cfg->host_budget_bytes, hipHostMallocDefault);
@@ -533,6 +659,8 @@ int vsm_server_create(const vsm_server_config* cfg, void** srv) {
     hipEvent_t ev;
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) s->step_ev.push_back(ev);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) s->small_ev.push_back(ev);
   }
   if (e != hipSuccess) {
     const int rc = note_hip_error(e);

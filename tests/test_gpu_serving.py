@@ -103,20 +103,53 @@ def test_staggered_arrivals_are_bit_identical(server, alone):
 
 
 def test_more_jobs_than_one_launch_holds():
-    """Seventy resident jobs: a step then spans two launches (at most 64 jobs each)."""
+    """130 resident small jobs: a small-lattice step then spans two launches (at
+    most 128 jobs each), and every job still gets the result it gets alone."""
     dims, prec, ns, seed = (8, 8, 8, 8), "fp32_bulk", 40, 21
     n, pairs = _inputs(dims, seed)
     kw = dict(pairs=pairs, n_sweeps=ns, precision=prec, measure_every=4, want_links=True, **KW)
-    with serve.Server(hbm_budget_bytes=1 << 30, host_budget_bytes=256 << 20, max_slots=80) as srv:
+    with serve.Server(hbm_budget_bytes=1 << 30, host_budget_bytes=512 << 20, max_slots=140) as srv:
         ref_id = srv.submit(dims, n, **kw)
         assert srv.wait(ref_id, 120)["state"] == "done"
         ref = srv.fetch(ref_id)
-        ids = [srv.submit(dims, n, **kw) for _ in range(70)]
+        ids = [srv.submit(dims, n, **kw) for _ in range(130)]
         for jid in ids:
             assert srv.wait(jid, 120)["state"] == "done"
             assert _same(ref, srv.fetch(jid))
         c = srv.counters()
-    assert c["peak_resident_jobs"] > 64
+    assert c["peak_resident_jobs"] > 128
+
+
+def test_small_lattices_run_whole_sweeps_per_launch():
+    """Lattices of at most 8192 sites are served by the persistent small-lattice
+    path: one workgroup per job runs all 16 passes of several sweeps (8 sweeps
+    of an 8^4 lattice per step), so four 8^4 jobs of 40 sweeps take a handful
+    of launches instead of one per subset pass (640 steps in pass-by-pass
+    batching), with the same links as the single-field path."""
+    dims, prec, ns = (8, 8, 8, 8), "fp64", 40
+    with serve.Server(hbm_budget_bytes=1 << 30, host_budget_bytes=256 << 20, max_slots=8) as srv:
+        ids = []
+        for k in range(4):
+            n, pairs = _inputs(dims, 31 + k)
+            ids.append(srv.submit(dims, n, pairs=pairs, n_sweeps=ns, precision=prec, measure_every=0,
+                                  want_links=True, **KW))
+        got = []
+        for jid in ids:
+            assert srv.wait(jid, 120)["state"] == "done"
+            got.append(srv.fetch(jid))
+        c = srv.counters()
+    print(f"4 jobs x {ns} sweeps of 8^4: {c['steps']} steps, {c['launches']} launches")
+    # admission (3 launches), final measurement and link read-back (2) per job, plus the steps
+    assert c["steps"] <= 2 * ns // 8
+    assert c["launches"] <= 4 * 5 + 2 * ns // 8
+    for k, (rec, links) in enumerate(got):
+        n, pairs = _inputs(dims, 31 + k)
+        f = api.Field(dims, prec, device=torch.device("cuda:0"), jacobi_workspace=False)
+        f.set_charges(n)
+        api.precondition(f, pairs, KW["omega"])
+        api.smooth(f, ns, KW["rho"], KW["eps"], order="annealed", vp=True)
+        assert np.abs(api.get_links(f).cpu().numpy() - links).max() < 1e-12
+        assert rec.flux_mismatch[-1] == 0
 
 
 def test_served_equals_single_field_path(alone):
