@@ -893,6 +893,7 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
     for (int mu = 0; mu < 4; ++mu) n0b |= (uint32_t)(z3[(size_t)g.perm[mu] * g.V + x] & 0xff) << (8 * mu);
     auto byte_at = [](uint32_t w, int i) { return (int)(int8_t)((w >> (8 * i)) & 0xffu); };
     // sector, finiteness and unitarity of an own link, once per link
+    // (U^dag U is Hermitian: its three diagonal entries and three entries above)
     auto own_checks = [&](const M3<double>& U, int mu) {
       const int sc = mcg_sector<GAUGE>(g, gauge, U, c, g.perm[mu]);
       secb |= (uint32_t)(sc & 0xff) << (8 * mu);
@@ -901,16 +902,36 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
       for (int e = 0; e < 9; ++e) fin = fin && isfinite(U.a[e].re) && isfinite(U.a[e].im);
       if (!fin) ++nonfin;
       if (sc == kUndef) ++undef;
-      const M3<double> uu = mul_dn(U, U);
 #pragma unroll
-      for (int e = 0; e < 9; ++e) {
-        const double dr = uu.a[e].re - ((e % 4 == 0) ? 1.0 : 0.0);
-        maxu2 = fmax(maxu2, fma(dr, dr, uu.a[e].im * uu.a[e].im));
+      for (int j = 0; j < 3; ++j) {
+        double d = -1.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d = fma(U.a[3 * i + j].re, U.a[3 * i + j].re, fma(U.a[3 * i + j].im, U.a[3 * i + j].im, d));
+        maxu2 = fmax(maxu2, d * d);
+#pragma unroll
+        for (int k = j + 1; k < 3; ++k) {
+          Cx<double> o = cx<double>(0.0, 0.0);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) cfma_c1(o, U.a[3 * i + j], U.a[3 * i + k]);
+          maxu2 = fmax(maxu2, fma(o.re, o.re, o.im * o.im));
+        }
       }
+    };
+    // <a, b> = sum_k a_k conj(b_k) of rows of two matrices
+    auto rdot = [](const M3<double>& a, int ra, const M3<double>& b, int rb) {
+      Cx<double> v = cx<double>(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) cfma_c2(v, a.a[3 * ra + k], b.a[3 * rb + k]);
+      return v;
     };
     // planes 01, 02, 03, 12, 13, 23 (user axes); the four links of a plaquette
     // are loaded together (rows 0 and 1), so one memory latency is exposed per
-    // plane; the own links of x come from cache after their first read
+    // plane; the own links of x come from cache after their first read.
+    // P = A B C^dag D^dag = X Y^dag with X = A B and Y = D C, both SU(3): rows 0
+    // and 1 of X and Y are products of two-row links with completed right
+    // factors, and the diagonal of X Y^dag is <x_i, y_i>, the third entry by
+    // the Binet-Cauchy identity <x0 x x1, y0 x y1> = <x0,y0><x1,y1> - <x0,y1><x1,y0>
+    // (row 2 of an SU(3) matrix is conj(row0 x row1)).
 #pragma unroll 1
     for (int p = 0; p < 6; ++p) {
       const int mu = p < 3 ? 0 : (p < 5 ? 1 : 2);
@@ -927,31 +948,22 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
       const M3<R> Cr = ld_rows(bmu, xn);
       const M3<R> Dr = ld_rows(bnu, x);
       load_fence();
-      const M3<double> A = mconvert<double>(full(Ar));
-      if (p == 0) own_checks(A, 0);
+      if (p == 0) own_checks(mconvert<double>(full(Ar)), 0);
+      if (mu == 0) own_checks(mconvert<double>(full(Dr)), nu);
       const M3<double> B = mconvert<double>(full(Br));
       const int sb = mcg_sector<GAUGE>(g, gauge, B, cm, dn);
-      M3<double> P = mul_nn(A, B);
+      const M3<double> X = mul2_nn(mconvert<double>(Ar), B);
       const M3<double> Cm = mconvert<double>(full(Cr));
       const int sc = mcg_sector<GAUGE>(g, gauge, Cm, cn, dm);
-      P = mul_nd(P, Cm);
-      const M3<double> D = mconvert<double>(full(Dr));
-      if (mu == 0) own_checks(D, nu);
-      // only the diagonal of P D^dag is needed: Re (P D^dag)_ii = sum_k Re P_ik conj(D_ik)
-      double dg[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        double v = P.a[3 * i].re * D.a[3 * i].re;
-        v = fma(P.a[3 * i].im, D.a[3 * i].im, v);
-#pragma unroll
-        for (int k = 1; k < 3; ++k) {
-          v = fma(P.a[3 * i + k].re, D.a[3 * i + k].re, v);
-          v = fma(P.a[3 * i + k].im, D.a[3 * i + k].im, v);
-        }
-        dg[i] = v;
-      }
-      const double rt = dg[0] + dg[1] + dg[2];
-      const double ra = (1.0 - dg[0]) + (1.0 - dg[1]) + (1.0 - dg[2]);
+      const M3<double> Y = mul2_nn(mconvert<double>(Dr), Cm);
+      const Cx<double> p00 = rdot(X, 0, Y, 0), p11 = rdot(X, 1, Y, 1);
+      const Cx<double> p01 = rdot(X, 0, Y, 1), p10 = rdot(X, 1, Y, 0);
+      double d2 = p00.re * p11.re;
+      d2 = fma(-p00.im, p11.im, d2);
+      d2 = fma(-p01.re, p10.re, d2);
+      d2 = fma(p01.im, p10.im, d2);
+      const double rt = p00.re + p11.re + d2;
+      const double ra = (1.0 - p00.re) + (1.0 - p11.re) + (1.0 - d2);
       kadd(kp, rt);
       kadd(ka, ra);
       const int smu = byte_at(secb, mu), snu = byte_at(secb, nu);
