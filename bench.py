@@ -330,6 +330,7 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=200, help="jobs of the serving stream (0: skip)")
     ap.add_argument("--serving-rate", type=float, default=50.0, help="mean arrivals per second")
     ap.add_argument("--serving-slots", type=int, default=64, help="jobs resident at once")
+    ap.add_argument("--no-serving-curve", action="store_true", help="skip the latency-versus-load replays")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB mebibytes (counter calibration), then 5 "
                          "reads, and print their rates")
@@ -420,7 +421,8 @@ def main():
         forms_out[p + "_flow_rk3"] = flow_form(dims, n, pairs, p)
     out["forms"] = forms_out
     if args.serving_jobs > 0:
-        out["serving"] = serving_leg(args.serving_jobs, args.serving_rate, args.serving_slots)
+        out["serving"] = serving_leg(args.serving_jobs, args.serving_rate, args.serving_slots,
+                                     loads=() if args.no_serving_curve else ((0.5, 120), (0.8, 150), (1.0, 150)))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(dims, n, pairs, args.cpu_threads)
     print(json.dumps(out), flush=True)
