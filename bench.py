@@ -251,6 +251,33 @@ def _serve_stream(n_jobs: int, rate: float, slots: int, seed: int) -> dict:
     return r
 
 
+def single_field_rates(precision="fp32_bulk", sweeps=8):
+    """Link updates per second of vsm_smooth alone on each serving lattice size
+    (the serving recipe, no measurement): what the stream would get if every
+    job ran by itself on the whole GPU."""
+    import torch
+
+    import fieldgen
+    from paper_2203_09764_amd import api
+
+    out = {}
+    for dims in fieldgen.SERVING_SIZES:
+        n = fieldgen.z3_vortex_charges(dims, 0.1, 7)
+        f = api.Field(dims, precision, device="cuda:0", jacobi_workspace=False)
+        f.set_charges(n)
+        api.precondition(f, fieldgen.centrifuge_pairs(dims, 8), 0.02)
+        api.smooth(f, 2, 0.06, -0.25, order="annealed", vp=True)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        api.smooth(f, sweeps, 0.06, -0.25, order="annealed", vp=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["x".join(str(v) for v in dims)] = round(4 * f.V * sweeps / (e0.elapsed_time(e1) * 1e-3), 1)
+    return out
+
+
 def serving_leg(n_jobs: int, rate: float, slots: int = 64, seed: int = 3,
                 loads=((0.5, 120), (0.8, 150), (1.0, 150))):
     """The serving stream: Poisson arrivals at `rate` jobs/s of smoothing jobs on
@@ -282,7 +309,25 @@ def serving_leg(n_jobs: int, rate: float, slots: int = 64, seed: int = 3,
                       "mean_queue_s": round(q["mean_queue_s"], 4), "lu_per_s": round(q["lu_per_s"], 1),
                       "offered_lu_per_s": round(q["offered_lu_per_s"], 1), "flux_mismatch_total": q["lost"]})
     out["latency_vs_load"] = curve
+    # the same sizes one at a time through vsm_smooth, and their mix weighted by
+    # the stream's link updates (what serving would reach with no batching cost)
+    single = single_field_rates()
+    out["single_field_lu_per_s"] = single
+    specs = fieldgen_mix(n_jobs, rate, seed)
+    tot = sum(specs.values())
+    out["single_field_mix_lu_per_s"] = round(tot / sum(lu / single[k] for k, lu in specs.items()), 1)
     return out
+
+
+def fieldgen_mix(n_jobs, rate, seed):
+    """Link updates of the stream per lattice size."""
+    import fieldgen
+
+    mix = {}
+    for sp in fieldgen.poisson_jobs(n_jobs, rate, seed):
+        k = "x".join(str(v) for v in sp.dims)
+        mix[k] = mix.get(k, 0) + 4 * fieldgen.volume(sp.dims) * sp.n_sweeps
+    return mix
 
 
 def cpu_baseline(dims, n, pairs, threads):
@@ -301,19 +346,23 @@ def cpu_baseline(dims, n, pairs, threads):
         dt += time.perf_counter() - t
         done += V // 4
         k += 1
-    model = "unknown"
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                key, _, val = line.partition(":")
+                key = key.strip()
+                if key in ("model name", "cpu MHz", "cpu cores", "siblings", "cache size") and key not in info:
+                    info[key] = val.strip()
     except OSError:
         pass
     return dict(value=done / dt, unit="link-updates/s", cores=int(used), kind="oracle",
                 sample=f"the first {k} annealing subset passes of the first sweep of the same "
                        f"preconditioned field: {done} link updates in {dt:.1f} s",
-                cpu_model=model, host_cpus=os.cpu_count())
+                cpu_model=info.get("model name", "unknown"), cpu_mhz=info.get("cpu MHz"),
+                cpu_cores_per_socket=info.get("cpu cores"), cpu_siblings=info.get("siblings"),
+                cpu_cache=info.get("cache size"), host_cpus=os.cpu_count(),
+                threads=int(used), build="gcc -O2 -fopenmp, FP64, OpenMP across the sites of one subset")
 
 
 def main():
