@@ -643,6 +643,10 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
     }
     rej = moved && !accept;
     if (jacobi || accept) {
+      // Chosen entry by entry: an if/else assigning whole matrices here made the
+      // gfx950 build of the vortex-preserving, gauge-undoing path store two
+      // entries of the old link (seen in the generated code and on the device).
+      // The random-gauge vortex-preservation tests cover this path.
       M3<R> outl;
 #pragma unroll
       for (int e = 0; e < 9; ++e) {
