@@ -242,6 +242,222 @@ __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm,
   chain_add(S, cr, w);
 }
 
+// ------------------------------------------------------------------ LDS ring
+
+// FP64 over-improved staples with the link loads staged through LDS.  A buffer
+// load with the lds flag writes each lane's 16 bytes straight into LDS (at M0 +
+// 16 lane), so a link in flight holds no registers; the link is read back
+// (ds_read_b128) just before its first use, and each such use issues the load
+// kRing links ahead into the slot it has just emptied.  The waits are explicit:
+// vector memory loads complete in order, so when a link is taken at most the
+// 6 (kRing - 1) entry loads issued after it may still be in flight.  The links
+// of one nu are taken in a fixed order (take_* below), 20 per nu, a multiple of
+// kRing, so that every take has a fixed slot; the loads issued ahead from the
+// last nu are the own link U (the first of them is the one used), which keeps
+// the number of loads in flight the same at every take.
+constexpr int kRing = 5;
+constexpr uint32_t kRingEntry = 64u * 16u;                   // one entry of a wave
+constexpr uint32_t kRingSlot = 6u * kRingEntry;              // one link of a wave
+constexpr uint32_t kRingWave = (uint32_t)kRing * kRingSlot;  // a wave's ring
+constexpr uint32_t kRingBytes = 4u * kRingWave;              // a block of four waves: 120 KiB
+static_assert(6 * (kRing - 1) == 24, "ring_take waits for vmcnt(24)");
+static_assert(20 % kRing == 0, "the 20 takes of one nu must fill whole turns of the ring");
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// The six entry loads of link idx of direction buffer b into the wave's slot
+// at LDS byte offset slot (uniform over the wave).
+__device__ __forceinline__ void ring_issue(const DirBuf<double>& b, uint32_t idx, uint32_t slot) {
+  const uint32_t voff = idx * 16u;
+#pragma unroll
+  for (int e = 0; e < 6; ++e)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(b.rs, (lds_void_t*)(uintptr_t)(slot + (uint32_t)e * kRingEntry), 16,
+                                             voff, (int)((uint32_t)e * b.estride), 0, 0);
+}
+
+// Rows 0 and 1 of the link in slot SLOT of the lane's ring (LDS byte offset
+// lane_ring), once it has landed: it is the oldest link in flight, and at most
+// the 24 entry loads issued after it may still be outstanding.  The LDS reads
+// wait for themselves in the same block.
+template <int SLOT>
+__device__ __forceinline__ M3<double> ring_take(uint32_t lane_ring) {
+  asm volatile("s_waitcnt vmcnt(24)" ::: "memory");
+  double2 v0, v1, v2, v3, v4, v5;
+  asm volatile(
+      "ds_read_b128 %0, %6 offset:%7\n\t"
+      "ds_read_b128 %1, %6 offset:%8\n\t"
+      "ds_read_b128 %2, %6 offset:%9\n\t"
+      "ds_read_b128 %3, %6 offset:%10\n\t"
+      "ds_read_b128 %4, %6 offset:%11\n\t"
+      "ds_read_b128 %5, %6 offset:%12\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3), "=&v"(v4), "=&v"(v5)
+      : "v"(lane_ring), "n"(SLOT * kRingSlot), "n"(SLOT * kRingSlot + kRingEntry),
+        "n"(SLOT * kRingSlot + 2 * kRingEntry), "n"(SLOT * kRingSlot + 3 * kRingEntry),
+        "n"(SLOT * kRingSlot + 4 * kRingEntry), "n"(SLOT * kRingSlot + 5 * kRingEntry)
+      : "memory");
+  M3<double> m;
+  m.a[0] = cx<double>(v0.x, v0.y);
+  m.a[1] = cx<double>(v1.x, v1.y);
+  m.a[2] = cx<double>(v2.x, v2.y);
+  m.a[3] = cx<double>(v3.x, v3.y);
+  m.a[4] = cx<double>(v4.x, v4.y);
+  m.a[5] = cx<double>(v5.x, v5.y);
+#pragma unroll
+  for (int e = 6; e < 9; ++e) m.a[e] = cx<double>(0.0, 0.0);
+  return m;
+}
+
+// Take order of the ten links of one orientation (the order of their first use
+// in staple_dir_shared): A D E F C B G H M N, as (direction mu?, a, b for +nu,
+// b for -nu) in x + a mu + b nu.
+__host__ __device__ constexpr bool take_mu(int k) {
+  constexpr bool t[10] = {false, false, true, false, false, true, true, false, false, true};
+  return t[k];
+}
+__host__ __device__ constexpr int take_a(int k) {
+  constexpr int t[10] = {0, 0, 0, 1, 1, 0, 1, 2, -1, -1};
+  return t[k];
+}
+__host__ __device__ constexpr int take_bu(int k) {
+  constexpr int t[10] = {0, 1, 2, 1, 0, 1, 1, 0, 0, 1};
+  return t[k];
+}
+__host__ __device__ constexpr int take_bd(int k) {
+  constexpr int t[10] = {-1, -2, -2, -2, -1, -1, -1, -1, -1, -1};
+  return t[k];
+}
+
+// The paths of staple_dir_shared for one orientation, with the same products
+// in the same order; issue(q) loads the link of take position q (this nu: 0-19,
+// the next: 20-24) into its slot.
+template <bool UP, typename Issue>
+__device__ __forceinline__ void ring_orient(M3<double>& S, double cp, double cr, const M3<double>& K,
+                                            const M3<double>& L, uint32_t lane_ring, Issue&& issue) {
+  constexpr int q0 = UP ? 0 : 10;
+#define take(k) ring_take<(k) % kRing>(lane_ring)
+  const M3<double> A = take(0);
+  issue(q0 + 5);
+  const M3<double> D = take(1);
+  issue(q0 + 6);
+  M3<double> w = UP ? mul2_nn(A, full(D)) : mul2_dd(full(A), full(D));
+  const M3<double> E = take(2);
+  issue(q0 + 7);
+  w = mul2_nn(w, full(E));
+  const M3<double> F = take(3);
+  issue(q0 + 8);
+  w = UP ? mul2_nd(w, full(F)) : mul2_nn(w, full(F));
+  const M3<double> C = take(4);
+  issue(q0 + 9);
+  const M3<double> Cf = full(C);
+  w = UP ? mul2_nd(w, Cf) : mul2_nn(w, Cf);
+  chain_add(S, cr, w);
+  const M3<double> B = take(5);
+  issue(q0 + 10);
+  const M3<double> Bf = full(B);
+  M3<double> T = UP ? mul2_nn(A, Bf) : mul2_dn(full(A), Bf);
+  chain_add(S, cp, UP ? mul2_nd(T, Cf) : mul2_nn(T, Cf));
+  const M3<double> G = take(6);
+  issue(q0 + 11);
+  T = mul2_nn(T, full(G));
+  const M3<double> H = take(7);
+  issue(q0 + 12);
+  T = UP ? mul2_nd(T, full(H)) : mul2_nn(T, full(H));
+  chain_add(S, cr, mul2_nd(T, full(K)));
+  const M3<double> M = take(8);
+  issue(q0 + 13);
+  w = UP ? mul2_dn(full(L), full(M)) : mul2_dd(full(L), full(M));
+  const M3<double> N = take(9);
+  issue(q0 + 14);
+  w = mul2_nn(w, full(N));
+  w = mul2_nn(w, Bf);
+  w = UP ? mul2_nd(w, Cf) : mul2_nn(w, Cf);
+  chain_add(S, cr, w);
+#undef take
+}
+
+// The over-improved staple sum of U_MU(x) (as staple_sum) and the own link U,
+// every link but K = U_mu(x+mu) and L = U_mu(x-mu) through the LDS ring.  The
+// block's dynamic LDS must hold kRingBytes.
+template <int MU>
+__device__ __forceinline__ void staple_ring(const Geo& g, const void* src, const int c[4], uint32_t x, double cp,
+                                            double cr, M3<double>& S, M3<double>& U) {
+  const DirBuf<double> bm = dir_buf<double>(src, g, MU);
+  Nb o;
+  o.S = (c[0] + c[1] + c[2] + c[3]) & 3;
+  o.dn[0] = o.dn[1] = o.dn[2] = o.dn[3] = o.dn[4] = 0;  // b = 0 (K, L) before a nu is set
+  o.j = x - (uint32_t)o.S * g.V4;
+  o.dm[0] = jdelta(g, MU, c[MU], -1);
+  o.dm[1] = 0;
+  o.dm[2] = jdelta(g, MU, c[MU], 1);
+  o.dm[3] = jdelta(g, MU, c[MU], 2);
+  const uint32_t ring = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kRingWave;
+  const uint32_t lane_ring = ring + (threadIdx.x & 63u) * 16u;
+  // K and L, held through every orientation: ordinary loads, issued first
+  const M3<double> K = ld_rows(bm, nbi(g, o, 1, 0));
+  const M3<double> L = ld_rows(bm, nbi(g, o, -1, 0));
+  load_fence();
+  auto set_nu = [&](int n) {
+    o.dn[0] = jdelta(g, n, c[n], -2);
+    o.dn[1] = jdelta(g, n, c[n], -1);
+    o.dn[2] = 0;
+    o.dn[3] = jdelta(g, n, c[n], 1);
+    o.dn[4] = jdelta(g, n, c[n], 2);
+  };
+  {
+    // the first five links of the first nu
+    const int n0 = MU == 0 ? 1 : 0;
+    set_nu(n0);
+    const DirBuf<double> b0 = dir_buf<double>(src, g, n0);
+#pragma unroll
+    for (int q = 0; q < kRing; ++q)
+      ring_issue(take_mu(q) ? bm : b0, nbi(g, o, take_a(q), take_bu(q)), ring + (uint32_t)q * kRingSlot);
+  }
+  S = mzero<double>();
+#pragma unroll 1
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == MU) continue;
+    set_nu(nu);
+    const DirBuf<double> bn = dir_buf<double>(src, g, nu);
+    // the next nu, whose first five links are issued from the end of this one;
+    // after the last nu the own link is issued instead
+    int nn = nu + 1;
+    if (nn == MU) ++nn;
+    const bool last = nn > 3;
+    const int nx = last ? nu : nn;  // a valid axis on the last nu (its offsets go unused)
+    const int dn1 = jdelta(g, nx, c[nx], 1), dn2 = jdelta(g, nx, c[nx], 2);
+    const DirBuf<double> bnn = dir_buf<double>(src, g, nx);
+    auto issue = [&](int q) {
+      const uint32_t slot = ring + (uint32_t)(q % kRing) * kRingSlot;
+      if (q < 20) {
+        const int k = q % 10;
+        ring_issue(take_mu(k) ? bm : bn, nbi(g, o, take_a(k), q < 10 ? take_bu(k) : take_bd(k)), slot);
+      } else if (last) {
+        ring_issue(bm, x, slot);
+      } else {
+        const int k = q - 20;
+        const int b = take_bu(k);
+        const uint32_t nidx = (uint32_t)((o.S + take_a(k) + b) & 3) * g.V4 +
+                              (uint32_t)((int)o.j + o.dm[take_a(k) + 1] + (b == 0 ? 0 : (b == 1 ? dn1 : dn2)));
+        ring_issue(take_mu(k) ? bm : bnn, nidx, slot);
+      }
+    };
+    ring_orient<true>(S, cp, cr, K, L, lane_ring, issue);
+    ring_orient<false>(S, cp, cr, K, L, lane_ring, issue);
+  }
+  // the own link went into the slot of take position 20 (slot 0); wait for
+  // every load issued after it too, so that no write into LDS is pending when
+  // the wave moves on
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  U = ring_take<0>(lane_ring);
+  rebuild_row2(U);
+}
+
+// Kernels whose launch allocates kRingBytes of dynamic LDS take the FP64
+// over-improved staples through the ring.
+template <typename R, bool OI>
+constexpr bool kUseRing = sizeof(R) == 8 && OI;
+
 // ------------------------------------------------------------------ updates
 
 // H = -i rho Q for the stout generator Q of Omega = Sigma U^dag: Hermitian and
@@ -482,6 +698,7 @@ __device__ __forceinline__ M3<R> staple_sum(const Geo& g, const void* src, const
   const DirBuf<R> bm = dir_buf<R>(src, g, MU);
   Nb o;
   o.S = (c[0] + c[1] + c[2] + c[3]) & 3;
+  o.dn[0] = o.dn[1] = o.dn[2] = o.dn[3] = o.dn[4] = 0;  // b = 0 (K, L) before a nu is set
   o.j = x - (uint32_t)o.S * g.V4;
   o.dm[0] = jdelta(g, MU, c[MU], -1);
   o.dm[1] = 0;
@@ -597,7 +814,7 @@ __device__ __forceinline__ bool chunk_site(const Geo& g, uint32_t t, int c[4]) {
 // transform, when one is given) equals the original charge (z3, canonical
 // layout: one byte per update, not worth a relayout).  Returns whether a
 // candidate was rejected.
-template <typename R, int MU, bool OI, int UPD>
+template <typename R, int MU, bool OI, int UPD, bool RING>
 __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* dst,
                                            const int8_t* __restrict__ z3,
                                            const double2* __restrict__ gauge, const UpdParams& p,
@@ -613,8 +830,14 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
   bool rej = false;
   if (active) {
     const uint32_t x = site_index(g, c);
-    const M3<R> S = staple_sum<R, MU, OI>(g, src, c, x, (R)p.cp, (R)p.cr);
-    const M3<R> U = ld_link(dir_buf<R>(src, g, MU), x);
+    M3<R> S, U;
+    if constexpr (RING) {
+      static_assert(sizeof(R) == 8 && OI, "the LDS ring serves the FP64 over-improved staples");
+      staple_ring<MU>(g, src, c, x, p.cp, p.cr, S, U);
+    } else {
+      S = staple_sum<R, MU, OI>(g, src, c, x, (R)p.cp, (R)p.cr);
+      U = ld_link(dir_buf<R>(src, g, MU), x);
+    }
     M3<double> cand;
     bool moved;
     if (UPD == 0)
@@ -668,7 +891,8 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* ds
                                                 int colour, int jacobi, uint32_t nthreads,
                                                 unsigned long long* __restrict__ rejected) {
   const uint32_t t = xcd_block() * blockDim.x + threadIdx.x;
-  const bool rej = update_one<R, MU, OI, UPD>(g, src, dst, z3, gauge, p, colour, jacobi, t, nthreads);
+  const bool rej = update_one<R, MU, OI, UPD, kUseRing<R, OI>>(g, src, dst, z3, gauge, p, colour, jacobi, t,
+                                                               nthreads);
   if (rejected) {
     const unsigned long long m = __ballot(rej);
     if ((threadIdx.x & 63u) == 0u && m) atomicAdd(rejected, (unsigned long long)__popcll(m));
@@ -679,9 +903,9 @@ __global__ void __launch_bounds__(256) k_update(Geo g, const void* src, void* ds
 // the step's block ranges; its threads run that job's subset pass with exactly
 // the per-link code of k_update, so a job's links do not depend on which other
 // jobs share the launch.  Stout updates only.
-template <typename R, int MU, bool OI>
+template <typename R, int MU, bool OI, bool RING>
 __device__ __forceinline__ bool batch_one(const ServeJob& J, int colour, uint32_t t) {
-  return update_one<R, MU, OI, 0>(J.g, J.links, J.links, J.z3, nullptr, J.p, colour, 0, t, J.g.V4);
+  return update_one<R, MU, OI, 0, RING>(J.g, J.links, J.links, J.z3, nullptr, J.p, colour, 0, t, J.g.V4);
 }
 
 template <typename R>
@@ -706,17 +930,17 @@ __global__ void __launch_bounds__(256) k_update_batch(const ServeJob* __restrict
   bool rej;
   if (J.p.oi) {
     switch (mu) {
-      case 0: rej = batch_one<R, 0, true>(J, colour, t); break;
-      case 1: rej = batch_one<R, 1, true>(J, colour, t); break;
-      case 2: rej = batch_one<R, 2, true>(J, colour, t); break;
-      default: rej = batch_one<R, 3, true>(J, colour, t); break;
+      case 0: rej = batch_one<R, 0, true, kUseRing<R, true>>(J, colour, t); break;
+      case 1: rej = batch_one<R, 1, true, kUseRing<R, true>>(J, colour, t); break;
+      case 2: rej = batch_one<R, 2, true, kUseRing<R, true>>(J, colour, t); break;
+      default: rej = batch_one<R, 3, true, kUseRing<R, true>>(J, colour, t); break;
     }
   } else {
     switch (mu) {
-      case 0: rej = batch_one<R, 0, false>(J, colour, t); break;
-      case 1: rej = batch_one<R, 1, false>(J, colour, t); break;
-      case 2: rej = batch_one<R, 2, false>(J, colour, t); break;
-      default: rej = batch_one<R, 3, false>(J, colour, t); break;
+      case 0: rej = batch_one<R, 0, false, false>(J, colour, t); break;
+      case 1: rej = batch_one<R, 1, false, false>(J, colour, t); break;
+      case 2: rej = batch_one<R, 2, false, false>(J, colour, t); break;
+      default: rej = batch_one<R, 3, false, false>(J, colour, t); break;
     }
   }
   const unsigned long long m = __ballot(rej);
@@ -748,17 +972,17 @@ __global__ void __launch_bounds__(256) k_serve_small(const ServeJob* __restrict_
           bool r;
           if (J.p.oi) {
             switch (mu) {
-              case 0: r = batch_one<R, 0, true>(J, colour, t); break;
-              case 1: r = batch_one<R, 1, true>(J, colour, t); break;
-              case 2: r = batch_one<R, 2, true>(J, colour, t); break;
-              default: r = batch_one<R, 3, true>(J, colour, t); break;
+              case 0: r = batch_one<R, 0, true, false>(J, colour, t); break;
+              case 1: r = batch_one<R, 1, true, false>(J, colour, t); break;
+              case 2: r = batch_one<R, 2, true, false>(J, colour, t); break;
+              default: r = batch_one<R, 3, true, false>(J, colour, t); break;
             }
           } else {
             switch (mu) {
-              case 0: r = batch_one<R, 0, false>(J, colour, t); break;
-              case 1: r = batch_one<R, 1, false>(J, colour, t); break;
-              case 2: r = batch_one<R, 2, false>(J, colour, t); break;
-              default: r = batch_one<R, 3, false>(J, colour, t); break;
+              case 0: r = batch_one<R, 0, false, false>(J, colour, t); break;
+              case 1: r = batch_one<R, 1, false, false>(J, colour, t); break;
+              case 2: r = batch_one<R, 2, false, false>(J, colour, t); break;
+              default: r = batch_one<R, 3, false, false>(J, colour, t); break;
             }
           }
           rej += r ? 1ull : 0ull;
@@ -1307,11 +1531,11 @@ void launch_update_mu(const Geo& g, const void* src, void* dst, const int8_t* z3
   const uint32_t n = jacobi ? g.V : g.V4;
   const unsigned nb = blocks_for(n, 256);
   const double2* gp = (const double2*)gauge;
-  // Occupancy: the pass is bound by refetches of links that other waves read
-  // too; fewer resident blocks per CU keep more of that reuse in L2.  Unused
-  // dynamic LDS caps the blocks per CU (160 KB of LDS): 1 for FP64 (4 waves),
-  // 2 for FP32 (8 waves), the best measured on the 48^3x96 pass.
-  const unsigned lds = p.oi ? (sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u) : 0u;
+  // Occupancy: fewer resident blocks per CU keep more of the links' reuse in
+  // L2.  Dynamic LDS caps the blocks per CU (160 KB of LDS): 1 for FP64 (4
+  // waves; the LDS is the staples' load ring), 2 for FP32 (8 waves, unused
+  // LDS), the best measured on the 48^3x96 pass.
+  const unsigned lds = p.oi ? (sizeof(R) == 8 ? kRingBytes : 54u * 1024u) : 0u;
   if (p.oi) {
     if (p.update == 0)
       hipLaunchKernelGGL((k_update<R, MU, true, 0>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
@@ -1349,8 +1573,9 @@ void launch_update_t(const Geo& g, const void* src, void* dst, const int8_t* z3,
 
 template <typename R>
 void launch_update_batch_t(const ServeJob* jobs, const BatchStep& step, uint32_t nblocks, hipStream_t st) {
-  // the same cap on resident blocks per CU as for single-field passes
-  const unsigned lds = sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u;
+  // the same cap on resident blocks per CU as for single-field passes (FP64:
+  // the LDS ring of the over-improved staples)
+  const unsigned lds = sizeof(R) == 8 ? kRingBytes : 54u * 1024u;
   const uint32_t nb8 = (nblocks + 7u) & ~7u;
   hipLaunchKernelGGL(k_update_batch<R>, dim3(nb8), dim3(256), lds, st, jobs, step);
 }
