@@ -956,7 +956,10 @@ __global__ void __launch_bounds__(256) k_update_batch(const ServeJob* __restrict
 // wait: the job lives in one workgroup.  Rejections are counted per wave into
 // the job's counter.
 template <typename R>
-__global__ void __launch_bounds__(256) k_serve_small(const ServeJob* __restrict__ jobs, SmallStep st) {
+constexpr unsigned kSmallThreads = sizeof(R) == 4 ? 512u : 256u;  // FP32 fits two waves per SIMD
+
+template <typename R>
+__global__ void __launch_bounds__(kSmallThreads<R>) k_serve_small(const ServeJob* __restrict__ jobs, SmallStep st) {
   if (blockIdx.x >= st.njobs) return;
   const ServeJob& J = jobs[st.slot[blockIdx.x]];
   const int nsw = st.sweeps[blockIdx.x];
@@ -1583,7 +1586,7 @@ void launch_update_batch_t(const ServeJob* jobs, const BatchStep& step, uint32_t
 template <typename R>
 void launch_serve_small_t(const ServeJob* jobs, const SmallStep& step, hipStream_t st) {
   if (step.njobs == 0) return;
-  hipLaunchKernelGGL(k_serve_small<R>, dim3(step.njobs), dim3(256), 0, st, jobs, step);
+  hipLaunchKernelGGL(k_serve_small<R>, dim3(step.njobs), dim3(kSmallThreads<R>), 0, st, jobs, step);
 }
 
 template <typename R, int MU>
