@@ -244,43 +244,55 @@ __device__ __forceinline__ void staple_dir_shared(M3<R>& S, const DirBuf<R>& bm,
 
 // ------------------------------------------------------------------ LDS ring
 
-// FP64 over-improved staples with the link loads staged through LDS.  A buffer
-// load with the lds flag writes each lane's 16 bytes straight into LDS (at M0 +
-// 16 lane), so a link in flight holds no registers; the link is read back
-// (ds_read_b128) just before its first use, and each such use issues the load
-// kRing links ahead into the slot it has just emptied.  The waits are explicit:
+// Over-improved staples with the link loads staged through LDS.  A buffer load
+// with the lds flag writes each lane's bytes straight into LDS (at M0 + lane
+// times the load size), so a link in flight holds no registers; the link is
+// read back just before its first use, and each such use issues the load kRing
+// links ahead into the slot it has just emptied.  The waits are explicit:
 // vector memory loads complete in order, so when a link is taken at most the
-// 6 (kRing - 1) entry loads issued after it may still be in flight.  The links
-// of one nu are taken in a fixed order (take_* below), 20 per nu, a multiple of
+// loads issued after it (kRing - 1 links) may still be in flight.  The links of
+// one nu are taken in a fixed order (take_* below), 20 per nu, a multiple of
 // kRing, so that every take has a fixed slot; the loads issued ahead from the
 // last nu are the own link U (the first of them is the one used), which keeps
 // the number of loads in flight the same at every take.
+// FP64 only: an entry (16 B) is one dwordx4 load, and a wave's slot is 6 entries
+// of 64 x 16 B.  (LDS loads come in 1, 2, 4, 12 and 16 bytes, so an FP32 entry
+// takes two loads; that ring measured a third slower than FP32 loads into
+// registers.)
 constexpr int kRing = 5;
-constexpr uint32_t kRingEntry = 64u * 16u;                   // one entry of a wave
-constexpr uint32_t kRingSlot = 6u * kRingEntry;              // one link of a wave
-constexpr uint32_t kRingWave = (uint32_t)kRing * kRingSlot;  // a wave's ring
-constexpr uint32_t kRingBytes = 4u * kRingWave;              // a block of four waves: 120 KiB
-static_assert(6 * (kRing - 1) == 24, "ring_take waits for vmcnt(24)");
 static_assert(20 % kRing == 0, "the 20 takes of one nu must fill whole turns of the ring");
+
+template <typename R>
+struct RingGeom;
+template <>
+struct RingGeom<double> {
+  static constexpr uint32_t slot = 6u * 64u * 16u;  // one link of a wave
+  static constexpr int loads = 6;                   // loads per link
+};
+template <typename R>
+constexpr uint32_t kRingWave = (uint32_t)kRing * RingGeom<R>::slot;  // a wave's ring
+template <typename R>
+constexpr uint32_t kRingBytes = 4u * kRingWave<R>;  // a block of four waves: 120 KiB
+static_assert(RingGeom<double>::loads * (kRing - 1) == 24, "the take waits for vmcnt(24)");
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// The six entry loads of link idx of direction buffer b into the wave's slot
-// at LDS byte offset slot (uniform over the wave).
+// The loads of link idx of direction buffer b into the wave's slot at LDS byte
+// offset slot (uniform over the wave).
 __device__ __forceinline__ void ring_issue(const DirBuf<double>& b, uint32_t idx, uint32_t slot) {
   const uint32_t voff = idx * 16u;
 #pragma unroll
   for (int e = 0; e < 6; ++e)
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(b.rs, (lds_void_t*)(uintptr_t)(slot + (uint32_t)e * kRingEntry), 16,
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(b.rs, (lds_void_t*)(uintptr_t)(slot + (uint32_t)e * 1024u), 16,
                                              voff, (int)((uint32_t)e * b.estride), 0, 0);
 }
 
-// Rows 0 and 1 of the link in slot SLOT of the lane's ring (LDS byte offset
-// lane_ring), once it has landed: it is the oldest link in flight, and at most
-// the 24 entry loads issued after it may still be outstanding.  The LDS reads
-// wait for themselves in the same block.
+// Rows 0 and 1 of the link in slot SLOT of the lane's ring, once it has landed:
+// it is the oldest link in flight, and at most the loads issued after it may
+// still be outstanding.  The LDS reads wait for themselves in the same block.
+// lane_ring: the LDS byte offset of the lane's first entry word in slot 0.
 template <int SLOT>
-__device__ __forceinline__ M3<double> ring_take(uint32_t lane_ring) {
+__device__ __forceinline__ M3<double> ring_take(uint32_t lane_ring, double) {
   asm volatile("s_waitcnt vmcnt(24)" ::: "memory");
   double2 v0, v1, v2, v3, v4, v5;
   asm volatile(
@@ -292,9 +304,8 @@ __device__ __forceinline__ M3<double> ring_take(uint32_t lane_ring) {
       "ds_read_b128 %5, %6 offset:%12\n\t"
       "s_waitcnt lgkmcnt(0)"
       : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3), "=&v"(v4), "=&v"(v5)
-      : "v"(lane_ring), "n"(SLOT * kRingSlot), "n"(SLOT * kRingSlot + kRingEntry),
-        "n"(SLOT * kRingSlot + 2 * kRingEntry), "n"(SLOT * kRingSlot + 3 * kRingEntry),
-        "n"(SLOT * kRingSlot + 4 * kRingEntry), "n"(SLOT * kRingSlot + 5 * kRingEntry)
+      : "v"(lane_ring), "n"(SLOT * 6144), "n"(SLOT * 6144 + 1024), "n"(SLOT * 6144 + 2048),
+        "n"(SLOT * 6144 + 3072), "n"(SLOT * 6144 + 4096), "n"(SLOT * 6144 + 5120)
       : "memory");
   M3<double> m;
   m.a[0] = cx<double>(v0.x, v0.y);
@@ -331,43 +342,43 @@ __host__ __device__ constexpr int take_bd(int k) {
 // The paths of staple_dir_shared for one orientation, with the same products
 // in the same order; issue(q) loads the link of take position q (this nu: 0-19,
 // the next: 20-24) into its slot.
-template <bool UP, typename Issue>
-__device__ __forceinline__ void ring_orient(M3<double>& S, double cp, double cr, const M3<double>& K,
-                                            const M3<double>& L, uint32_t lane_ring, Issue&& issue) {
+template <typename R, bool UP, typename Issue>
+__device__ __forceinline__ void ring_orient(M3<R>& S, R cp, R cr, const M3<R>& K, const M3<R>& L,
+                                            uint32_t lane_ring, Issue&& issue) {
   constexpr int q0 = UP ? 0 : 10;
-#define take(k) ring_take<(k) % kRing>(lane_ring)
-  const M3<double> A = take(0);
+#define take(k) ring_take<(k) % kRing>(lane_ring, R())
+  const M3<R> A = take(0);
   issue(q0 + 5);
-  const M3<double> D = take(1);
+  const M3<R> D = take(1);
   issue(q0 + 6);
-  M3<double> w = UP ? mul2_nn(A, full(D)) : mul2_dd(full(A), full(D));
-  const M3<double> E = take(2);
+  M3<R> w = UP ? mul2_nn(A, full(D)) : mul2_dd(full(A), full(D));
+  const M3<R> E = take(2);
   issue(q0 + 7);
   w = mul2_nn(w, full(E));
-  const M3<double> F = take(3);
+  const M3<R> F = take(3);
   issue(q0 + 8);
   w = UP ? mul2_nd(w, full(F)) : mul2_nn(w, full(F));
-  const M3<double> C = take(4);
+  const M3<R> C = take(4);
   issue(q0 + 9);
-  const M3<double> Cf = full(C);
+  const M3<R> Cf = full(C);
   w = UP ? mul2_nd(w, Cf) : mul2_nn(w, Cf);
   chain_add(S, cr, w);
-  const M3<double> B = take(5);
+  const M3<R> B = take(5);
   issue(q0 + 10);
-  const M3<double> Bf = full(B);
-  M3<double> T = UP ? mul2_nn(A, Bf) : mul2_dn(full(A), Bf);
+  const M3<R> Bf = full(B);
+  M3<R> T = UP ? mul2_nn(A, Bf) : mul2_dn(full(A), Bf);
   chain_add(S, cp, UP ? mul2_nd(T, Cf) : mul2_nn(T, Cf));
-  const M3<double> G = take(6);
+  const M3<R> G = take(6);
   issue(q0 + 11);
   T = mul2_nn(T, full(G));
-  const M3<double> H = take(7);
+  const M3<R> H = take(7);
   issue(q0 + 12);
   T = UP ? mul2_nd(T, full(H)) : mul2_nn(T, full(H));
   chain_add(S, cr, mul2_nd(T, full(K)));
-  const M3<double> M = take(8);
+  const M3<R> M = take(8);
   issue(q0 + 13);
   w = UP ? mul2_dn(full(L), full(M)) : mul2_dd(full(L), full(M));
-  const M3<double> N = take(9);
+  const M3<R> N = take(9);
   issue(q0 + 14);
   w = mul2_nn(w, full(N));
   w = mul2_nn(w, Bf);
@@ -378,11 +389,11 @@ __device__ __forceinline__ void ring_orient(M3<double>& S, double cp, double cr,
 
 // The over-improved staple sum of U_MU(x) (as staple_sum) and the own link U,
 // every link but K = U_mu(x+mu) and L = U_mu(x-mu) through the LDS ring.  The
-// block's dynamic LDS must hold kRingBytes.
-template <int MU>
-__device__ __forceinline__ void staple_ring(const Geo& g, const void* src, const int c[4], uint32_t x, double cp,
-                                            double cr, M3<double>& S, M3<double>& U) {
-  const DirBuf<double> bm = dir_buf<double>(src, g, MU);
+// block's dynamic LDS must hold kRingBytes<R>.
+template <typename R, int MU>
+__device__ __forceinline__ void staple_ring(const Geo& g, const void* src, const int c[4], uint32_t x, R cp, R cr,
+                                            M3<R>& S, M3<R>& U) {
+  const DirBuf<R> bm = dir_buf<R>(src, g, MU);
   Nb o;
   o.S = (c[0] + c[1] + c[2] + c[3]) & 3;
   o.dn[0] = o.dn[1] = o.dn[2] = o.dn[3] = o.dn[4] = 0;  // b = 0 (K, L) before a nu is set
@@ -391,11 +402,11 @@ __device__ __forceinline__ void staple_ring(const Geo& g, const void* src, const
   o.dm[1] = 0;
   o.dm[2] = jdelta(g, MU, c[MU], 1);
   o.dm[3] = jdelta(g, MU, c[MU], 2);
-  const uint32_t ring = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kRingWave;
-  const uint32_t lane_ring = ring + (threadIdx.x & 63u) * 16u;
+  const uint32_t ring = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kRingWave<R>;
+  const uint32_t lane_ring = ring + (threadIdx.x & 63u) * (sizeof(R) == 8 ? 16u : 4u);
   // K and L, held through every orientation: ordinary loads, issued first
-  const M3<double> K = ld_rows(bm, nbi(g, o, 1, 0));
-  const M3<double> L = ld_rows(bm, nbi(g, o, -1, 0));
+  const M3<R> K = ld_rows(bm, nbi(g, o, 1, 0));
+  const M3<R> L = ld_rows(bm, nbi(g, o, -1, 0));
   load_fence();
   auto set_nu = [&](int n) {
     o.dn[0] = jdelta(g, n, c[n], -2);
@@ -408,17 +419,17 @@ __device__ __forceinline__ void staple_ring(const Geo& g, const void* src, const
     // the first five links of the first nu
     const int n0 = MU == 0 ? 1 : 0;
     set_nu(n0);
-    const DirBuf<double> b0 = dir_buf<double>(src, g, n0);
+    const DirBuf<R> b0 = dir_buf<R>(src, g, n0);
 #pragma unroll
     for (int q = 0; q < kRing; ++q)
-      ring_issue(take_mu(q) ? bm : b0, nbi(g, o, take_a(q), take_bu(q)), ring + (uint32_t)q * kRingSlot);
+      ring_issue(take_mu(q) ? bm : b0, nbi(g, o, take_a(q), take_bu(q)), ring + (uint32_t)q * RingGeom<R>::slot);
   }
-  S = mzero<double>();
+  S = mzero<R>();
 #pragma unroll 1
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == MU) continue;
     set_nu(nu);
-    const DirBuf<double> bn = dir_buf<double>(src, g, nu);
+    const DirBuf<R> bn = dir_buf<R>(src, g, nu);
     // the next nu, whose first five links are issued from the end of this one;
     // after the last nu the own link is issued instead
     int nn = nu + 1;
@@ -426,9 +437,14 @@ __device__ __forceinline__ void staple_ring(const Geo& g, const void* src, const
     const bool last = nn > 3;
     const int nx = last ? nu : nn;  // a valid axis on the last nu (its offsets go unused)
     const int dn1 = jdelta(g, nx, c[nx], 1), dn2 = jdelta(g, nx, c[nx], 2);
-    const DirBuf<double> bnn = dir_buf<double>(src, g, nx);
+    const DirBuf<R> bnn = dir_buf<R>(src, g, nx);
     auto issue = [&](int q) {
-      const uint32_t slot = ring + (uint32_t)(q % kRing) * kRingSlot;
+      // the ring base is read again at each issue (an empty asm that may change
+      // it), so that the compiler forms the LDS addresses where they are used
+      // instead of holding all of them in scalar registers through the loop
+      uint32_t rg = ring;
+      asm volatile("" : "+s"(rg));
+      const uint32_t slot = rg + (uint32_t)(q % kRing) * RingGeom<R>::slot;
       if (q < 20) {
         const int k = q % 10;
         ring_issue(take_mu(k) ? bm : bn, nbi(g, o, take_a(k), q < 10 ? take_bu(k) : take_bd(k)), slot);
@@ -442,21 +458,23 @@ __device__ __forceinline__ void staple_ring(const Geo& g, const void* src, const
         ring_issue(take_mu(k) ? bm : bnn, nidx, slot);
       }
     };
-    ring_orient<true>(S, cp, cr, K, L, lane_ring, issue);
-    ring_orient<false>(S, cp, cr, K, L, lane_ring, issue);
+    ring_orient<R, true>(S, cp, cr, K, L, lane_ring, issue);
+    ring_orient<R, false>(S, cp, cr, K, L, lane_ring, issue);
   }
   // the own link went into the slot of take position 20 (slot 0); wait for
   // every load issued after it too, so that no write into LDS is pending when
   // the wave moves on
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  U = ring_take<0>(lane_ring);
+  U = ring_take<0>(lane_ring, R());
   rebuild_row2(U);
 }
 
-// Kernels whose launch allocates kRingBytes of dynamic LDS take the FP64
-// over-improved staples through the ring.
+// k_update, whose launch allocates kRingBytes<double> of dynamic LDS in FP64,
+// takes the FP64 over-improved staples through the ring.  The serving step
+// kernel does not: with the bodies of all four directions in one kernel the
+// ring's code left it with a thousand spilled registers.
 template <typename R, bool OI>
-constexpr bool kUseRing = sizeof(R) == 8 && OI;
+constexpr bool kUseRing = OI && sizeof(R) == 8;
 
 // ------------------------------------------------------------------ updates
 
@@ -832,8 +850,8 @@ __device__ __forceinline__ bool update_one(const Geo& g, const void* src, void* 
     const uint32_t x = site_index(g, c);
     M3<R> S, U;
     if constexpr (RING) {
-      static_assert(sizeof(R) == 8 && OI, "the LDS ring serves the FP64 over-improved staples");
-      staple_ring<MU>(g, src, c, x, p.cp, p.cr, S, U);
+      static_assert(OI, "the LDS ring serves the over-improved staples");
+      staple_ring<R, MU>(g, src, c, x, (R)p.cp, (R)p.cr, S, U);
     } else {
       S = staple_sum<R, MU, OI>(g, src, c, x, (R)p.cp, (R)p.cr);
       U = ld_link(dir_buf<R>(src, g, MU), x);
@@ -930,10 +948,10 @@ __global__ void __launch_bounds__(256) k_update_batch(const ServeJob* __restrict
   bool rej;
   if (J.p.oi) {
     switch (mu) {
-      case 0: rej = batch_one<R, 0, true, kUseRing<R, true>>(J, colour, t); break;
-      case 1: rej = batch_one<R, 1, true, kUseRing<R, true>>(J, colour, t); break;
-      case 2: rej = batch_one<R, 2, true, kUseRing<R, true>>(J, colour, t); break;
-      default: rej = batch_one<R, 3, true, kUseRing<R, true>>(J, colour, t); break;
+      case 0: rej = batch_one<R, 0, true, false>(J, colour, t); break;
+      case 1: rej = batch_one<R, 1, true, false>(J, colour, t); break;
+      case 2: rej = batch_one<R, 2, true, false>(J, colour, t); break;
+      default: rej = batch_one<R, 3, true, false>(J, colour, t); break;
     }
   } else {
     switch (mu) {
@@ -1535,10 +1553,10 @@ void launch_update_mu(const Geo& g, const void* src, void* dst, const int8_t* z3
   const unsigned nb = blocks_for(n, 256);
   const double2* gp = (const double2*)gauge;
   // Occupancy: fewer resident blocks per CU keep more of the links' reuse in
-  // L2.  Dynamic LDS caps the blocks per CU (160 KB of LDS): 1 for FP64 (4
+  // L2.  Dynamic LDS (160 KB per CU) caps the blocks per CU: 1 for FP64 (4
   // waves; the LDS is the staples' load ring), 2 for FP32 (8 waves, unused
   // LDS), the best measured on the 48^3x96 pass.
-  const unsigned lds = p.oi ? (sizeof(R) == 8 ? kRingBytes : 54u * 1024u) : 0u;
+  const unsigned lds = p.oi ? (sizeof(R) == 8 ? kRingBytes<double> : 54u * 1024u) : 0u;
   if (p.oi) {
     if (p.update == 0)
       hipLaunchKernelGGL((k_update<R, MU, true, 0>), dim3(nb), dim3(256), lds, st, g, src, dst, z3, gp, p,
@@ -1576,9 +1594,9 @@ void launch_update_t(const Geo& g, const void* src, void* dst, const int8_t* z3,
 
 template <typename R>
 void launch_update_batch_t(const ServeJob* jobs, const BatchStep& step, uint32_t nblocks, hipStream_t st) {
-  // the same cap on resident blocks per CU as for single-field passes (FP64:
-  // the LDS ring of the over-improved staples)
-  const unsigned lds = sizeof(R) == 8 ? kRingBytes : 54u * 1024u;
+  // the same cap on resident blocks per CU as for single-field passes (unused
+  // dynamic LDS)
+  const unsigned lds = sizeof(R) == 8 ? 96u * 1024u : 54u * 1024u;
   const uint32_t nb8 = (nblocks + 7u) & ~7u;
   hipLaunchKernelGGL(k_update_batch<R>, dim3(nb8), dim3(256), lds, st, jobs, step);
 }
