@@ -81,18 +81,22 @@ __global__ void k_load_z3(Geo g, const int8_t* __restrict__ z3, void* links) {
 //   lambda^j = lambda + omega (sigma - lambda),  lambda^k = lambda - omega (sigma - lambda),
 // i.e. e^{i lambda^j} = z(n) e^{+i d}, e^{i lambda^k} = z(n) e^{-i d} with
 // d = omega (2 pi / 18) (m - 6 n), and the third phase stays lambda.  m is the
-// exact integer sum of the 18 neighbouring charges of the six staples.  The
-// thread works on user direction mu and canonical site s.
+// exact integer sum of the 18 neighbouring charges of the six staples.  Threads
+// run over the internal layout (internal direction dmu, link index idx), so that
+// a wave's link stores are contiguous; the charges, the pair and m are read and
+// written in the canonical order of user direction mu and site s.
 template <typename R>
 __global__ void k_centrifuge(Geo g, const int8_t* __restrict__ z3, const int8_t* __restrict__ pair,
                              double omega, void* links, int32_t* __restrict__ m_out) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= 4u * g.V) return;
-  const int mu = (int)(tid / g.V);
-  const uint32_t s = tid - (uint32_t)mu * g.V;
+  const int dmu = (int)(tid / g.V);
+  const uint32_t idx = tid - (uint32_t)dmu * g.V;
   int c[4];
-  coords_of_canonical(g, s, c);
-  const int dmu = g.perm[mu];
+  coords_of_index(g, idx, c);
+  const int mu = g.uperm[dmu];
+  const uint32_t s = canonical_index(g, c);
+  const uint32_t lk = (uint32_t)mu * g.V + s;  // the link in canonical order
   // charge of user direction d at the site shifted by (i along mu, k along nu)
   auto nat = [&](int d, int i, int k, int dnu) -> int {
     int e[4] = {c[0], c[1], c[2], c[3]};
@@ -107,14 +111,14 @@ __global__ void k_centrifuge(Geo g, const int8_t* __restrict__ z3, const int8_t*
     m += nat(nu, 0, 0, dnu) + nat(mu, 0, 1, dnu) - nat(nu, 1, 0, dnu);     // upper staple
     m += -nat(nu, 0, -1, dnu) + nat(mu, 0, -1, dnu) + nat(nu, 1, -1, dnu);  // lower staple
   }
-  const int n = z3[tid];
+  const int n = z3[lk];
   const double d = omega * (2.0 * 3.14159265358979323846 / 18.0) * (double)(m - 6 * n);
   double sd, cd;
   sincos(d, &sd, &cd);
   const Cx<double> z = z3_elem(n);
   const Cx<double> zp = cx<double>(z.re * cd - z.im * sd, z.re * sd + z.im * cd);
   const Cx<double> zm = cx<double>(z.re * cd + z.im * sd, z.im * cd - z.re * sd);
-  const int j = pair[tid];
+  const int j = pair[lk];
   const int k = (j + 1) % 3;
   M3<R> u = mzero<R>();
 #pragma unroll
@@ -122,8 +126,8 @@ __global__ void k_centrifuge(Geo g, const int8_t* __restrict__ z3, const int8_t*
     const Cx<double> v = (i == j) ? zp : ((i == k) ? zm : z);
     u.a[4 * i] = cx<R>((R)v.re, (R)v.im);
   }
-  st_link<R>(links, g, dmu, site_index(g, c), u);
-  if (m_out) m_out[tid] = m;
+  st_link<R>(links, g, dmu, idx, u);
+  if (m_out) m_out[lk] = m;
 }
 
 // ------------------------------------------------------------------ gauge transform
