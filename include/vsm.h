@@ -12,8 +12,8 @@
  * Conventions for every call
  *   dims[4]   lattice extents (Lx, Ly, Lz, Lt), host array.  Every extent must be
  *             >= 4 and a multiple of 4 (the annealing subsets need it).
- *             6 * V * sizeof(entry) must stay below 2^31 bytes (V < 22.3M
- *             sites in FP64, < 44.7M in FP32).
+ *             6 * (V + 64) * sizeof(entry) must stay below 2^31 bytes
+ *             (V < 22.3M sites in FP64, < 44.7M in FP32).
  *   site      s = x + Lx*(y + Ly*(z + Lz*t)); direction mu = 0..3 = (x, y, z, t).
  *   precision VSM_FP64 (all arithmetic and storage FP64) or VSM_FP32_BULK
  *             (links stored and staples / products computed in FP32; the

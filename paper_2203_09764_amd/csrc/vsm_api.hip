@@ -53,7 +53,7 @@ int vsm_check_dims(const int32_t dims[4], int32_t order, int32_t precision) {
 size_t vsm_links_bytes(const int32_t dims[4], int32_t precision) {
   if (check_dims_impl(dims, VSM_JACOBI, precision) != VSM_OK) return 0;
   const Geo g = make_geo(dims);
-  return 24ull * g.V * entry_bytes(precision);
+  return 24ull * g.es * entry_bytes(precision);
 }
 
 size_t vsm_workspace_bytes(const int32_t dims[4], int32_t precision, int32_t order) {
@@ -160,7 +160,7 @@ int smooth_impl(const int32_t dims[4], int32_t precision, void* links_dev, const
   }
   if (cur != links_dev) {
     const hipError_t e =
-        hipMemcpyAsync(links_dev, cur, 24ull * g.V * entry_bytes(precision), hipMemcpyDeviceToDevice, st);
+        hipMemcpyAsync(links_dev, cur, 24ull * g.es * entry_bytes(precision), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return note_hip_error(e);
   }
   return hip_status();
@@ -250,7 +250,7 @@ int vsm_flow(const int32_t dims[4], int32_t precision, void* links_dev, void* wo
   }
   if (cur != links_dev) {
     const hipError_t e =
-        hipMemcpyAsync(links_dev, cur, 24ull * g.V * entry_bytes(precision), hipMemcpyDeviceToDevice, st);
+        hipMemcpyAsync(links_dev, cur, 24ull * g.es * entry_bytes(precision), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return note_hip_error(e);
   }
   return hip_status();

@@ -29,6 +29,10 @@ namespace vsm {
 
 constexpr int kUndef = -128;
 constexpr uint32_t kStoredEntries = 6;  // rows 0 and 1 of each link
+// Gap after each entry array, in entries.  Without it, at extents such as
+// 48^3 x 96 the arrays start 2^21-byte multiples apart, and a wave's six entry
+// loads of one link fall on the same L2 channels; 64 entries measured best.
+constexpr uint32_t kEntryPad = 64;
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9-family raw buffer descriptor
 
 // ------------------------------------------------------------------ complex
@@ -241,6 +245,7 @@ struct Geo {
   int perm[4];     // internal axis of user axis mu
   int uperm[4];    // user axis of internal axis d
   int T1, T2, T3;  // traversal tiles: rows of axis 1 (T1) with rows of axis 2 (T2) or axis 3 (T3)
+  uint32_t es;     // entries from one entry array of a direction to the next: V + kEntryPad
 };
 
 // Axes 1..3 of the r-th row (x1, x2, x3) in traversal order (a row is the
@@ -341,17 +346,17 @@ struct R2<float> {
   using type = float2;
 };
 
-// One direction's 9 entry arrays as a raw buffer resource: voffset = idx*sizeof(R2)
-// in a VGPR, soffset = e*V*sizeof(R2) in an SGPR.
+// One direction's 6 stored entry arrays as a raw buffer resource: voffset =
+// idx*sizeof(R2) in a VGPR, soffset = e*es*sizeof(R2) in an SGPR.
 template <typename R>
 struct DirBuf {
   __amdgpu_buffer_rsrc_t rs;
-  uint32_t estride;  // bytes between entry arrays = V * sizeof(R2)
+  uint32_t estride;  // bytes between entry arrays = es * sizeof(R2)
 };
 
 template <typename R>
 __device__ __forceinline__ DirBuf<R> dir_buf(const void* links, const Geo& g, int mu) {
-  const uint32_t es = g.V * (uint32_t)sizeof(typename R2<R>::type);
+  const uint32_t es = g.es * (uint32_t)sizeof(typename R2<R>::type);
   const char* base = (const char*)links + (size_t)mu * kStoredEntries * (size_t)es;
   DirBuf<R> b;
   b.rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(kStoredEntries * es),
@@ -443,13 +448,13 @@ __device__ __forceinline__ M3<R> full(const M3<R>& m) {
 template <typename R>
 __device__ __forceinline__ void st_link(void* links, const Geo& g, int mu, uint32_t idx, const M3<R>& m) {
   using T2 = typename R2<R>::type;
-  T2* p = (T2*)links + (size_t)mu * kStoredEntries * g.V + idx;
+  T2* p = (T2*)links + (size_t)mu * kStoredEntries * g.es + idx;
 #pragma unroll
   for (int e = 0; e < 6; ++e) {
     T2 v;
     v.x = m.a[e].re;
     v.y = m.a[e].im;
-    p[(size_t)e * g.V] = v;
+    p[(size_t)e * g.es] = v;
   }
 }
 

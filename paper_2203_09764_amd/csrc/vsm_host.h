@@ -34,7 +34,7 @@ inline int check_dims_impl(const int32_t dims[4], int32_t order, int32_t precisi
     if (dims[d] < 4 || dims[d] % 4) return VSM_E_DIMS;
     V *= (uint64_t)dims[d];
   }
-  if (6ull * V * entry_bytes(precision) >= (1ull << 31)) return VSM_E_DIMS;
+  if (6ull * (V + kEntryPad) * entry_bytes(precision) >= (1ull << 31)) return VSM_E_DIMS;
   return VSM_OK;
 }
 
@@ -70,6 +70,7 @@ inline Geo make_geo(const int32_t dims[4]) {
   g.Xq = g.L[0] / 4;
   g.V = acc;
   g.V4 = g.V / 4;
+  g.es = g.V + kEntryPad;
   g.jst[0] = 1;
   g.jst[1] = (uint32_t)g.Xq;
   g.jst[2] = (uint32_t)g.Xq * (uint32_t)g.L[1];
@@ -112,7 +113,7 @@ inline WsLayout ws_layout(const int32_t dims[4], int32_t precision, int32_t orde
   w.charges = align256(w.partials + (size_t)measure_blocks(g) * partial_bytes());
   w.field = align256(w.charges + 4ull * g.V);
   w.total = w.field;
-  if (order == VSM_JACOBI) w.total += align256(24ull * g.V * entry_bytes(precision));
+  if (order == VSM_JACOBI) w.total += align256(24ull * g.es * entry_bytes(precision));
   return w;
 }
 

@@ -89,7 +89,7 @@ JobLayout layout_of(const vsm_job& j) {
   JobLayout L;
   size_t o = 0;
   L.links = o;
-  o += align256(24ull * V * entry_bytes(j.precision));
+  o += align256(24ull * g.es * entry_bytes(j.precision));
   L.z3 = o;
   o += align256(4ull * V);
   L.pairs = o;

@@ -56,13 +56,14 @@ def test_version_and_errors():
 def test_sizes(prec, entry):
     dims = (8, 12, 16, 4)
     V = 8 * 12 * 16 * 4
-    # rows 0 and 1 of 4 links per site
-    assert lib().vsm_links_bytes(dims_arg(dims), prec) == 24 * V * entry
+    # rows 0 and 1 of 4 links per site, each of the 24 entry arrays followed by
+    # a gap of 64 entries
+    assert lib().vsm_links_bytes(dims_arg(dims), prec) == 24 * (V + 64) * entry
     ann = lib().vsm_workspace_bytes(dims_arg(dims), prec, ANNEALED)
     jac = lib().vsm_workspace_bytes(dims_arg(dims), prec, JACOBI)
     # counters, measurement partials, the charges in the internal layout
     assert 256 + 4 * V < ann < 256 + 80 * (V // 256 + 1) + 4 * V + 512
-    assert jac >= ann + 24 * V * entry
+    assert jac >= ann + 24 * (V + 64) * entry
 
 
 @pytest.mark.parametrize("dims", [(8, 8, 8, 6), (2, 8, 8, 8), (8, 8, 8, 0), (8, 8, 8, -4)])
@@ -72,7 +73,7 @@ def test_bad_extents(dims):
 
 
 def test_volume_limit():
-    # 6 V * 16 bytes must stay below 2^31
+    # 6 (V + 64) * 16 bytes must stay below 2^31
     assert lib().vsm_check_dims(dims_arg((64, 64, 64, 92)), ANNEALED, FP64) == E_DIMS
     assert lib().vsm_check_dims(dims_arg((64, 64, 64, 92)), ANNEALED, FP32_BULK) == 0
     assert lib().vsm_check_dims(dims_arg((8, 8, 8, 8)), ANNEALED, 7) == E_PARAM
@@ -134,12 +135,12 @@ def test_server_job_footprint():
     V = 8 ** 4
     base = lib().vsm_server_job_bytes(j)
     # links (FP32 rows 0, 1), charges, pairs, workspace, one record
-    assert base >= 24 * V * 8 + 4 * V + 4 * V + 256
+    assert base >= 24 * (V + 64) * 8 + 4 * V + 4 * V + 256
     j.want_links = 1
     assert lib().vsm_server_job_bytes(j) == base + 4 * V * 9 * 16
     j.want_links = 0
     j.precision = FP64
-    assert lib().vsm_server_job_bytes(j) == base + 24 * V * 8
+    assert lib().vsm_server_job_bytes(j) == base + 24 * (V + 64) * 8
     host = lib().vsm_server_host_bytes(j)
     assert host >= 8 * V + 64
 
