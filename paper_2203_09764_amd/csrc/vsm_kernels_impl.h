@@ -1177,18 +1177,29 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
       for (int k = 0; k < 3; ++k) cfma_c2(v, a.a[3 * ra + k], b.a[3 * rb + k]);
       return v;
     };
-    // planes 01, 02, 03, 12, 13, 23 (user axes); the four links of a plaquette
-    // are loaded together (rows 0 and 1), so one memory latency is exposed per
-    // plane; the own links of x come from cache after their first read.
+    // Planes in the order 01, 02, 03, 13, 12, 23 (user axes), so that each plane
+    // after the first shares an own link of x with the plane before: that link
+    // is held over (held), the plane loads the other own link and its two
+    // neighbour links together (rows 0 and 1), and one memory latency is
+    // exposed per plane.  An own link read again after more planes would have
+    // left the L2 by then; in this order x's own links are read 7 times instead
+    // of 12.
     // P = A B C^dag D^dag = X Y^dag with X = A B and Y = D C, both SU(3): rows 0
     // and 1 of X and Y are products of two-row links with completed right
     // factors, and the diagonal of X Y^dag is <x_i, y_i>, the third entry by
     // the Binet-Cauchy identity <x0 x x1, y0 x y1> = <x0,y0><x1,y1> - <x0,y1><x1,y0>
     // (row 2 of an SU(3) matrix is conj(row0 x row1)).
+    M3<R> held = mzero<R>();
 #pragma unroll 1
-    for (int p = 0; p < 6; ++p) {
-      const int mu = p < 3 ? 0 : (p < 5 ? 1 : 2);
-      const int nu = p < 3 ? p + 1 : (p < 5 ? p - 1 : 3);
+    for (int q = 0; q < 6; ++q) {
+      // plane q of this order: (mu, nu), its index in the flux array, and
+      // which own link comes from the plane before (1: U_mu, 2: U_nu) and is
+      // kept for the next (1: U_mu, 2: U_nu)
+      const int mu = q < 3 ? 0 : (q < 5 ? 1 : 2);
+      const int nu = q < 3 ? q + 1 : (q == 3 ? 3 : (q == 4 ? 2 : 3));
+      const int p = q == 3 ? 4 : (q == 4 ? 3 : q);
+      const int from = q == 0 ? 0 : (q == 3 ? 2 : 1);
+      const int keep = (q == 2 || q == 4) ? 2 : 1;
       const int dm = g.perm[mu], dn = g.perm[nu];
       const DirBuf<R> bmu = dir_buf<R>(links, g, dm), bnu = dir_buf<R>(links, g, dn);
       int cm[4] = {c[0], c[1], c[2], c[3]};
@@ -1196,12 +1207,14 @@ __global__ void __launch_bounds__(256) k_measure(Geo g, const void* links, const
       int cn[4] = {c[0], c[1], c[2], c[3]};
       cn[dn] = wrap_add(cn[dn], 1, g.L[dn]);
       const uint32_t xm = site_index(g, cm), xn = site_index(g, cn);
-      const M3<R> Ar = ld_rows(bmu, x);
+      M3<R> Ar = held, Dr = held;
+      if (from != 1) Ar = ld_rows(bmu, x);
       const M3<R> Br = ld_rows(bnu, xm);
       const M3<R> Cr = ld_rows(bmu, xn);
-      const M3<R> Dr = ld_rows(bnu, x);
+      if (from != 2) Dr = ld_rows(bnu, x);
       load_fence();
-      if (p == 0) own_checks(mconvert<double>(full(Ar)), 0);
+      held = keep == 1 ? Ar : Dr;
+      if (q == 0) own_checks(mconvert<double>(full(Ar)), 0);
       if (mu == 0) own_checks(mconvert<double>(full(Dr)), nu);
       const M3<double> B = mconvert<double>(full(Br));
       const int sb = mcg_sector<GAUGE>(g, gauge, B, cm, dn);
