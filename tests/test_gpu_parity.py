@@ -177,6 +177,25 @@ def test_single_pass_full_su3(eps, mu, colour):
     assert err < LINK_TOL
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_bulk", 2e-6)])
+def test_jacobi_overimproved_stout_full_su3(precision, tol):
+    """Two smearing sweeps (every link from the previous sweep's field) of
+    over-improved stout on a Haar-random field: the FP64 staples go through the
+    LDS load ring with distinct source and destination buffers."""
+    dims = (8, 4, 8, 12)
+    U = _haar(dims, 140)
+    n = fieldgen.z3_vortex_charges(dims, 0.1, 12)
+    f = _field(dims, precision)
+    f.set_charges(n)
+    api.set_links(f, torch.from_numpy(U))
+    api.smooth(f, 2, 0.1, -0.25, order="jacobi")
+    want = U.copy()
+    ora.smooth(dims, want, n, 2, order="jacobi", rho=0.1, eps=-0.25, measure_every=0)
+    err = np.abs(_links(f) - want).max()
+    print(f"{precision}: max link error {err:.2e}")
+    assert err < tol
+
+
 def test_c0_jacobi_plain_stout():
     """8^4 vortex field (p = 0.05), centrifuge 0.02, 10 plain stout sweeps rho = 0.1."""
     c = fieldgen.CONFIGS["c0"]
