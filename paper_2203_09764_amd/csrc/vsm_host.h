@@ -95,6 +95,14 @@ inline Geo make_geo(const int32_t dims[4]) {
       g.T3 = t;
       break;
     }
+  // Lattices of at most 2^19 sites (the serving sizes) take their rows in plain
+  // order, one tile: with many of them in one serving step this measured 5%
+  // faster than tiles, and a single such lattice runs as fast either way.
+  if (g.V <= (1u << 19)) {
+    g.T1 = g.L[1];
+    g.T2 = g.L[2];
+    g.T3 = g.L[3];
+  }
   return g;
 }
 
