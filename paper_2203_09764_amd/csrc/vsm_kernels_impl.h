@@ -322,63 +322,62 @@ __device__ __forceinline__ void staple_dir_loads(M3<R>& S, const DirBuf<R>& bm, 
 }
 
 // The FP32 form's staples: the grouping of orient_paths with the 2x1 left
-// path multiplied out in full,
-//   Z = cp A B + cr A D E F^dag + cr L^dag M (N B),   S += Z C^dag + cr A B G H^dag K^dag
+// path multiplied out in full and the links loaded in the order of their
+// first use (A D E F B G H M N C),
+//   Z = cp A B + cr A D E F^dag + cr L^dag M N B,   S += Z C^dag + cr A B G H^dag K^dag
 // (for -nu: A, D, F, H, M walked backwards): ten 2-row products and one 3-row
-// product, with no partial product beyond N B needing its row 2.  The loads
-// keep the pairs of orient_paths' order together (A H, N G, M C) while the
-// products take the links nearly in the order of first use, so that only H is
-// held long.  FP32's pass is bound by its arithmetic as much as by its reads:
-// orient_paths saves 4% of the FP32 reads but takes more instructions and 70
-// more registers, and measured 3% slower; this order saves 3% of the reads
-// against the order of first use at the same instruction count.
+// product, and no partial product beyond the paths needs its row 2.  FP32's
+// pass is bound by its arithmetic as much as by its reads.  orient_paths saves
+// 4% of the FP32 reads but takes more instructions and 70 more registers, and
+// measured 3% slower on 48^3x96; issuing this path's loads with the pairs of
+// orient_paths' order together (A H D E F B N G M C) saved 3% of the reads at
+// the same instruction count, and measured 5% slower on 32^3x64.
 template <typename R, bool UP>
 __device__ __forceinline__ void staple_dir_factored(M3<R>& S, const DirBuf<R>& bm, const DirBuf<R>& bn,
                                                     const Geo& g, const Nb& o, R cp, R cr,
                                                     const M3<R>& Kf, const M3<R>& Lf) {
   auto I = [&](int a, int b) { return nbi(g, o, a, b); };
   const int sg = UP ? 1 : -1;
-  // loads in the order A H D E F B N G M C
+  // 1x2: A D E F^dag
   const M3<R> Ar = ld_rows(bn, I(0, UP ? 0 : -1));
-  const M3<R> Hr = ld_rows(bn, I(2, UP ? 0 : -1));
   const M3<R> Dr = ld_rows(bn, I(0, UP ? 1 : -2));
-  load_fence();
   const M3<R> Er = ld_rows(bm, I(0, 2 * sg));
   load_fence();
-  // 1x2: A D E F^dag
+  const M3<R> Fr = ld_rows(bn, I(1, UP ? 1 : -2));
+  load_fence();
   M3<R> Af;
   if (!UP) Af = full(Ar);
   M3<R> w = UP ? mul2_nn(Ar, full(Dr)) : mul2_dd(Af, full(Dr));
-  const M3<R> Fr = ld_rows(bn, I(1, UP ? 1 : -2));
+  const M3<R> Br = ld_rows(bm, I(0, sg));
   load_fence();
   w = mul2_nn(w, full(Er));
-  const M3<R> Br = ld_rows(bm, I(0, sg));
+  const M3<R> Gr = ld_rows(bm, I(1, sg));
   load_fence();
   w = UP ? mul2_nd(w, full(Fr)) : mul2_nn(w, full(Fr));
   rebuild_row2(w);
   M3<R> Z;
 #pragma unroll
   for (int e = 0; e < 9; ++e) Z.a[e] = cx<R>(cr * w.a[e].re, cr * w.a[e].im);
-  const M3<R> Nr = ld_rows(bm, I(-1, sg));
-  load_fence();
   // plaquette A B, and 2x1 left A B G H^dag K^dag, share T = A B
+  const M3<R> Hr = ld_rows(bn, I(2, UP ? 0 : -1));
+  load_fence();
   const M3<R> Bf = full(Br);
   M3<R> T = UP ? mul2_nn(Ar, Bf) : mul2_dn(Af, Bf);
   rebuild_row2(T);
   maxpy(Z, cp, T);
-  const M3<R> Gr = ld_rows(bm, I(1, sg));
-  load_fence();
-  // 2x1 middle L^dag M (N B): N B now, so that B need not be held further
-  const M3<R> NB = mul2_nn(Nr, Bf);
   const M3<R> Mr = ld_rows(bn, I(-1, UP ? 0 : -1));
   load_fence();
   T = mul2_nn(T, full(Gr));
-  const M3<R> Cr = ld_rows(bn, I(1, UP ? 0 : -1));
+  const M3<R> Nr = ld_rows(bm, I(-1, sg));
   load_fence();
   T = UP ? mul2_nd(T, full(Hr)) : mul2_nn(T, full(Hr));
+  const M3<R> Cr = ld_rows(bn, I(1, UP ? 0 : -1));
+  load_fence();
   chain_add(S, cr, mul2_nd(T, Kf));
+  // 2x1 middle: L^dag M N B
   w = UP ? mul2_dn(Lf, full(Mr)) : mul2_dd(Lf, full(Mr));
-  w = mul2_nn(w, full(NB));
+  w = mul2_nn(w, full(Nr));
+  w = mul2_nn(w, Bf);
   rebuild_row2(w);
   maxpy(Z, cr, w);
   madd_prod<R, UP>(S, Z, full(Cr));
