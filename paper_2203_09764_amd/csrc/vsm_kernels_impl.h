@@ -199,9 +199,9 @@ __device__ __forceinline__ uint32_t nbi(const Geo& g, const Nb& o, int a, int b)
 // (direction mu?, a, b for +nu, b for -nu) in x + a mu + b nu:
 //   D = U_nu(x+nu)  E = U_mu(x+2nu)  F = U_nu(x+mu+nu)  B = U_mu(x+nu)  A = U_nu(x)
 //   H = U_nu(x+2mu)  N = U_mu(x-mu+nu)  G = U_mu(x+mu+nu)  M = U_nu(x-mu)  C = U_nu(x+mu)
-// (for -nu, b as listed).  The update of x + 2mu, in the same subset and two
-// rows of the traversal away, needs A, N, M of x's as its H, G, C: loading
-// each such pair back to back lets the two updates' requests for the same line
+// (for -nu, the b of take_bd: the same paths with nu reversed).  The update of x + 2mu, in the same subset and two
+// rows of the traversal away, needs x's H, G, C as its A, N, M: loading each
+// such pair back to back lets the two updates' requests for the same line
 // meet in the L2.  A model of one XCD's L2 replaying the loads of the blocks
 // in flight puts this order 13-17% below the order of first use in fetched
 // lines; measured on 48^3x96 in FP64, a pass fetches 8% less (10.9 to 10.1 GB).
