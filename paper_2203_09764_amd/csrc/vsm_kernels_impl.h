@@ -199,12 +199,13 @@ __device__ __forceinline__ uint32_t nbi(const Geo& g, const Nb& o, int a, int b)
 // (direction mu?, a, b for +nu, b for -nu) in x + a mu + b nu:
 //   D = U_nu(x+nu)  E = U_mu(x+2nu)  F = U_nu(x+mu+nu)  B = U_mu(x+nu)  A = U_nu(x)
 //   H = U_nu(x+2mu)  N = U_mu(x-mu+nu)  G = U_mu(x+mu+nu)  M = U_nu(x-mu)  C = U_nu(x+mu)
-// (for -nu, the b of take_bd: the same paths with nu reversed).  The update of x + 2mu, in the same subset and two
-// rows of the traversal away, needs x's H, G, C as its A, N, M: loading each
-// such pair back to back lets the two updates' requests for the same line
-// meet in the L2.  A model of one XCD's L2 replaying the loads of the blocks
-// in flight puts this order 13-17% below the order of first use in fetched
-// lines; measured on 48^3x96 in FP64, a pass fetches 8% less (10.9 to 10.1 GB).
+// (for -nu, the b of take_bd: the same paths with nu reversed).  The update
+// of x + 2mu, in the same subset and two rows of the traversal away, needs
+// x's H, G, C as its A, N, M: loading each such pair back to back lets the
+// two updates' requests for the same line meet in the L2.  A model of one
+// XCD's L2 replaying the loads of the blocks in flight puts this order 13-17%
+// below the order of first use in fetched lines; measured on 48^3x96 in FP64,
+// a pass fetches 8% less (10.9 to 10.1 GB).
 __host__ __device__ constexpr bool take_mu(int k) {
   constexpr bool t[10] = {false, true, false, true, false, false, true, true, false, false};
   return t[k];
@@ -252,7 +253,7 @@ __device__ __forceinline__ void madd_prod(M3<R>& S, const M3<R>& x, const M3<R>&
 //   - the plaquette's A B starts the 2x1 left path, A B G (H^dag K^dag).
 // (For -nu: A, D, F, H, M walked backwards.)  Every factor is formed as soon
 // as the load order above has delivered its links, so that few are held:
-// nine 2-row products and one 3-row product, against thirteen 2-row products
+// ten 2-row products and one 3-row product, against thirteen 2-row products
 // path by path.  Each path and partial product is a product of SU(3) links, so
 // its row 2 is rebuilt from rows 0 and 1 where it is needed.  get(Take<k>())
 // returns rows 0 and 1 of link k of the load order; K = U_mu(x+mu) and
@@ -392,8 +393,8 @@ __device__ __forceinline__ void staple_dir_factored(M3<R>& S, const DirBuf<R>& b
 // links ahead into the slot it has just emptied.  The waits are explicit:
 // vector memory loads complete in order, so when a link is taken at most the
 // loads issued after it (kRing - 1 links) may still be in flight.  The links of
-// one nu are taken in the load order of orient_paths (take_*), 20 per nu, a multiple of
-// kRing, so that every take has a fixed slot; the loads issued ahead from the
+// one nu are taken in the load order of orient_paths (take_*), 20 per nu, a
+// multiple of kRing, so that every take has a fixed slot; the loads issued ahead from the
 // last nu are the own link U (the first of them is the one used), which keeps
 // the number of loads in flight the same at every take.
 // FP64 only: an entry (16 B) is one dwordx4 load, and a wave's slot is 6 entries
