@@ -15,23 +15,29 @@
 // direction mu != 0 then fill long contiguous runs of j (the subset is
 // s = (colour - c_mu) mod 4), and so does every neighbour of them.
 // Links are SU(3), so only rows 0 and 1 are stored; row 2 is rebuilt on load as
-// conj(row0 x row1).  Each direction owns 6 arrays of V complex entries
-// (entry e = 3 * row + column, rows 0 and 1):
-//   entry e of link (mu, idx) lives at element (mu * 6 + e) * V + idx,
-// stored as R2 = {re, im}; a wave reads 64 consecutive idx of one entry in one
-// 1 KiB (FP64) or 512 B (FP32) request.  A link costs 96 B (FP64) or 48 B (FP32).
+// conj(row0 x row1).  The six stored entries (e = 3 * row + column, rows 0
+// and 1) go into 16-byte words: one entry per word in FP64 ({re, im}), two in
+// FP32 ({re, im} of entries 2w and 2w + 1).  Each direction owns one array of
+// V words per word of a link (6 in FP64, 3 in FP32):
+//   word w of link (mu, idx) lives at element (mu * W + w) * V + idx,
+// so that a wave reads 64 consecutive idx of one word in one 1 KiB request,
+// 16 bytes per lane, in either form.  A link costs 96 B (FP64) or 48 B (FP32).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace vsm {
 
 constexpr int kUndef = -128;
-constexpr uint32_t kStoredEntries = 6;  // rows 0 and 1 of each link
-// Gap after each entry array, in entries.  Without it, at extents such as
-// 48^3 x 96 the arrays start 2^21-byte multiples apart, and a wave's six entry
-// loads of one link fall on the same L2 channels; 64 entries measured best.
+// 16-byte words per stored link (rows 0 and 1): 6 in FP64, 3 in FP32.
+template <typename R>
+constexpr uint32_t kLinkWords = (uint32_t)(12 * sizeof(R) / 16);
+// Gap after each word array, in words.  Without it, at extents such as
+// 48^3 x 96 the arrays start 2^21-byte multiples apart, and a wave's six word
+// loads of one link fall on the same L2 channels; 64 words measured best.
 constexpr uint32_t kEntryPad = 64;
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // gfx9-family raw buffer descriptor
 
@@ -335,50 +341,45 @@ __device__ __forceinline__ int jdelta(const Geo& g, int d, int v, int k) {
 
 // ------------------------------------------------------------------ link access
 
-template <typename R>
-struct R2 {};
-template <>
-struct R2<double> {
-  using type = double2;
-};
-template <>
-struct R2<float> {
-  using type = float2;
-};
-
-// One direction's 6 stored entry arrays as a raw buffer resource: voffset =
-// idx*sizeof(R2) in a VGPR, soffset = e*es*sizeof(R2) in an SGPR.
+// One direction's word arrays as a raw buffer resource: voffset = idx * 16 in
+// a VGPR, soffset = w * es * 16 in an SGPR.
 template <typename R>
 struct DirBuf {
   __amdgpu_buffer_rsrc_t rs;
-  uint32_t estride;  // bytes between entry arrays = es * sizeof(R2)
+  uint32_t estride;  // bytes between word arrays = es * 16
 };
 
 template <typename R>
 __device__ __forceinline__ DirBuf<R> dir_buf(const void* links, const Geo& g, int mu) {
-  const uint32_t es = g.es * (uint32_t)sizeof(typename R2<R>::type);
-  const char* base = (const char*)links + (size_t)mu * kStoredEntries * (size_t)es;
+  const uint32_t es = g.es * 16u;
+  const char* base = (const char*)links + (size_t)mu * kLinkWords<R> * (size_t)es;
   DirBuf<R> b;
-  b.rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(kStoredEntries * es),
+  b.rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(kLinkWords<R> * es),
                                            (int)kRsrcWord3);
   b.estride = es;
   return b;
 }
 
-__device__ __forceinline__ void ld_entry(const DirBuf<double>& b, uint32_t voff, int e, Cx<double>& out) {
-  auto v = __builtin_amdgcn_raw_buffer_load_b128(b.rs, voff, (int)(e * b.estride), 0);
-  double2 d;
-  __builtin_memcpy(&d, &v, sizeof d);
-  out.re = d.x;
-  out.im = d.y;
+// Rows 0 and 1 of the link at voffset voff into m.a[0..5].
+__device__ __forceinline__ void ld_words(const DirBuf<double>& b, uint32_t voff, M3<double>& m) {
+#pragma unroll
+  for (int w = 0; w < 6; ++w) {
+    auto v = __builtin_amdgcn_raw_buffer_load_b128(b.rs, voff, (int)(w * b.estride), 0);
+    double2 d;
+    __builtin_memcpy(&d, &v, sizeof d);
+    m.a[w] = cx<double>(d.x, d.y);
+  }
 }
 
-__device__ __forceinline__ void ld_entry(const DirBuf<float>& b, uint32_t voff, int e, Cx<float>& out) {
-  auto v = __builtin_amdgcn_raw_buffer_load_b64(b.rs, voff, (int)(e * b.estride), 0);
-  float2 d;
-  __builtin_memcpy(&d, &v, sizeof d);
-  out.re = d.x;
-  out.im = d.y;
+__device__ __forceinline__ void ld_words(const DirBuf<float>& b, uint32_t voff, M3<float>& m) {
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    auto v = __builtin_amdgcn_raw_buffer_load_b128(b.rs, voff, (int)(w * b.estride), 0);
+    float4 d;
+    __builtin_memcpy(&d, &v, sizeof d);
+    m.a[2 * w] = cx<float>(d.x, d.y);
+    m.a[2 * w + 1] = cx<float>(d.z, d.w);
+  }
 }
 
 // Row 2 of an SU(3) matrix from rows 0 and 1: r2 = conj(r0 x r1).
@@ -406,9 +407,7 @@ __device__ __forceinline__ void rebuild_row2(M3<R>& m) {
 template <typename R>
 __device__ __forceinline__ M3<R> ld_link(const DirBuf<R>& b, uint32_t idx) {
   M3<R> m;
-  const uint32_t voff = idx * (uint32_t)sizeof(typename R2<R>::type);
-#pragma unroll
-  for (int e = 0; e < 6; ++e) ld_entry(b, voff, e, m.a[e]);
+  ld_words(b, idx * 16u, m);
   rebuild_row2(m);
   return m;
 }
@@ -419,9 +418,7 @@ __device__ __forceinline__ M3<R> ld_link(const DirBuf<R>& b, uint32_t idx) {
 template <typename R>
 __device__ __forceinline__ M3<R> ld_rows(const DirBuf<R>& b, uint32_t idx) {
   M3<R> m;
-  const uint32_t voff = idx * (uint32_t)sizeof(typename R2<R>::type);
-#pragma unroll
-  for (int e = 0; e < 6; ++e) ld_entry(b, voff, e, m.a[e]);
+  ld_words(b, idx * 16u, m);
 #pragma unroll
   for (int e = 6; e < 9; ++e) m.a[e] = cx<R>(R(0), R(0));
   return m;
@@ -445,17 +442,22 @@ __device__ __forceinline__ M3<R> full(const M3<R>& m) {
   return f;
 }
 
+__device__ __forceinline__ void st_words(double2* p, size_t es, const M3<double>& m) {
+#pragma unroll
+  for (int w = 0; w < 6; ++w) p[(size_t)w * es] = make_double2(m.a[w].re, m.a[w].im);
+}
+
+__device__ __forceinline__ void st_words(float4* p, size_t es, const M3<float>& m) {
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+    p[(size_t)w * es] = make_float4(m.a[2 * w].re, m.a[2 * w].im, m.a[2 * w + 1].re, m.a[2 * w + 1].im);
+}
+
 template <typename R>
 __device__ __forceinline__ void st_link(void* links, const Geo& g, int mu, uint32_t idx, const M3<R>& m) {
-  using T2 = typename R2<R>::type;
-  T2* p = (T2*)links + (size_t)mu * kStoredEntries * g.es + idx;
-#pragma unroll
-  for (int e = 0; e < 6; ++e) {
-    T2 v;
-    v.x = m.a[e].re;
-    v.y = m.a[e].im;
-    p[(size_t)e * g.es] = v;
-  }
+  using W = typename std::conditional<sizeof(R) == 8, double2, float4>::type;
+  W* p = (W*)links + (size_t)mu * kLinkWords<R> * g.es + idx;
+  st_words(p, g.es, m);
 }
 
 // ------------------------------------------------------------------ centre sector
