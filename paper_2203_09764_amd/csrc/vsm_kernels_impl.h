@@ -394,9 +394,9 @@ __device__ __forceinline__ void staple_dir_factored(M3<R>& S, const DirBuf<R>& b
 // vector memory loads complete in order, so when a link is taken at most the
 // loads issued after it (kRing - 1 links) may still be in flight.  The links of
 // one nu are taken in the load order of orient_paths (take_*), 20 per nu, a
-// multiple of kRing, so that every take has a fixed slot; the loads issued ahead from the
-// last nu are the own link U (the first of them is the one used), which keeps
-// the number of loads in flight the same at every take.
+// multiple of kRing, so that every take has a fixed slot.  After the last nu
+// the own link U is issued once, at position 20, and the last takes wait for
+// exactly the loads issued after them.
 // FP64 only: an entry (16 B) is one dwordx4 load, and a wave's slot is 6 entries
 // of 64 x 16 B.  (LDS loads come in 1, 2, 4, 12 and 16 bytes, so an FP32 entry
 // takes two loads; that ring measured a third slower than FP32 loads into
@@ -415,7 +415,7 @@ template <typename R>
 constexpr uint32_t kRingWave = (uint32_t)kRing * RingGeom<R>::slot;  // a wave's ring
 template <typename R>
 constexpr uint32_t kRingBytes = 4u * kRingWave<R>;  // a block of four waves: 120 KiB
-static_assert(RingGeom<double>::loads * (kRing - 1) == 24, "the take waits for vmcnt(24)");
+static_assert(RingGeom<double>::loads * (kRing - 1) == 24, "a take waits for vmcnt(24)");
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -429,13 +429,18 @@ __device__ __forceinline__ void ring_issue(const DirBuf<double>& b, uint32_t idx
                                              voff, (int)((uint32_t)e * b.estride), 0, 0);
 }
 
-// Rows 0 and 1 of the link in slot SLOT of the lane's ring, once it has landed:
-// it is the oldest link in flight, and at most the loads issued after it may
-// still be outstanding.  The LDS reads wait for themselves in the same block.
+// Waits until at most N vector loads are outstanding: those issued after the
+// link about to be taken, which is then the oldest in flight and has landed.
+template <int N>
+__device__ __forceinline__ void ring_wait() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Rows 0 and 1 of the link in slot SLOT of the lane's ring, once ring_wait has
+// seen it land.  The LDS reads wait for themselves in the same block.
 // lane_ring: the LDS byte offset of the lane's first entry word in slot 0.
 template <int SLOT>
 __device__ __forceinline__ M3<double> ring_take(uint32_t lane_ring, double) {
-  asm volatile("s_waitcnt vmcnt(24)" ::: "memory");
   double2 v0, v1, v2, v3, v4, v5;
   asm volatile(
       "ds_read_b128 %0, %6 offset:%7\n\t"
@@ -464,14 +469,19 @@ __device__ __forceinline__ M3<double> ring_take(uint32_t lane_ring, double) {
 // orient_paths with the links taken from the ring in the load order; each
 // take issues the load kRing links ahead into the slot it has just emptied
 // (issue(q) loads the link of take position q: this nu 0-19, the next 20-24).
-template <typename R, bool UP, typename Issue>
+// After the last nu only the own link follows (position 20), so there the
+// takes of positions 17-19 wait for the 3, 2, 1 links issued after them.
+template <typename R, bool UP, bool LAST, typename Issue>
 __device__ __forceinline__ void ring_orient(M3<R>& S, R cp, R cr, const M3<R>& K, const M3<R>& L,
                                             uint32_t lane_ring, Issue&& issue) {
   constexpr int q0 = UP ? 0 : 10;
   auto get = [&](auto pos) {
     constexpr int k = decltype(pos)::value;
+    constexpr int q = q0 + k;
+    constexpr int after = LAST && q > 20 - kRing ? 20 - q : kRing - 1;  // links issued after q
+    ring_wait<RingGeom<R>::loads * after>();
     const M3<R> m = ring_take<k % kRing>(lane_ring, R());
-    issue(q0 + k + kRing);
+    if constexpr (!LAST || q + kRing <= 20) issue(q + kRing);
     return m;
   };
   orient_paths<R, UP>(S, cp, cr, K, L, get);
@@ -548,8 +558,11 @@ __device__ __forceinline__ void staple_ring(const Geo& g, const void* src, const
         ring_issue(take_mu(k) ? bm : bnn, nidx, slot);
       }
     };
-    ring_orient<R, true>(S, cp, cr, K, L, lane_ring, issue);
-    ring_orient<R, false>(S, cp, cr, K, L, lane_ring, issue);
+    ring_orient<R, true, false>(S, cp, cr, K, L, lane_ring, issue);
+    if (last)
+      ring_orient<R, false, true>(S, cp, cr, K, L, lane_ring, issue);
+    else
+      ring_orient<R, false, false>(S, cp, cr, K, L, lane_ring, issue);
   }
   // the own link went into the slot of take position 20 (slot 0); wait for
   // every load issued after it too, so that no write into LDS is pending when
