@@ -398,9 +398,12 @@ __device__ __forceinline__ void staple_dir_factored(M3<R>& S, const DirBuf<R>& b
 // the own link U is issued once, at position 20, and the last takes wait for
 // exactly the loads issued after them.
 // FP64 only: an entry (16 B) is one dwordx4 load, and a wave's slot is 6 entries
-// of 64 x 16 B.  (LDS loads come in 1, 2, 4, 12 and 16 bytes, so an FP32 entry
-// takes two loads; that ring measured a third slower than FP32 loads into
-// registers.)
+// of 64 x 16 B.  (When FP32 links were stored one entry per 8-byte word, an
+// FP32 ring took 12 loads per link and measured a third slower than FP32 loads
+// into registers.  FP32 now stores 16-byte words as well, but it takes the
+// staples of staple_dir_factored, whose fewer instructions and registers matter
+// more to its pass than a deeper prefetch, and the serving kernels share that
+// path with the single-field pass.)
 constexpr int kRing = 5;
 static_assert(20 % kRing == 0, "the 20 takes of one nu must fill whole turns of the ring");
 
